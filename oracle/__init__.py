@@ -1,0 +1,170 @@
+"""CPU oracle for the blocked / sectorized Bloom filter -- TEST INFRASTRUCTURE.
+
+Only the test suite, the package smoke check and the CPU-baseline leg of the
+benchmark may import this module.  It wraps ``bf_oracle.c`` (plain
+single-threaded C, the definition of what the GPU path computes) through
+ctypes and shares nothing with the HIP library.
+
+The filter definition follows "Optimizing Bloom Filters on Modern GPUs"
+(arXiv 2512.15595): Sec. II-A-2/3/4 for the blocked, register-blocked and
+sectorized layouts, Sec. IV-B for one xxHash64 base hash per key and salted
+multiplicative bit positions.  ``bf_oracle.h`` lists the readings taken where
+the paper is silent.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "bf_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+SALT_SEED = 0x73746C61732D6662
+MAX_K = 32
+
+
+def build(force: bool = False) -> str:
+    """Compile bf_oracle.c into liboracle.so with gcc (host code only)."""
+    if force or not os.path.exists(_LIB_PATH) or (
+        os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC)
+    ):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC",
+             "-o", tmp, _SRC]
+        )
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        lib = ctypes.CDLL(build())
+        u64, u32, i32 = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+        vp = ctypes.c_void_p
+        lib.oracle_xxh64.argtypes = [vp, ctypes.c_size_t, u64]
+        lib.oracle_xxh64.restype = u64
+        lib.oracle_hash_key.argtypes = [u64, u64]
+        lib.oracle_hash_key.restype = u64
+        lib.oracle_salts.argtypes = [vp]
+        lib.oracle_salts.restype = None
+        lib.oracle_check_params.argtypes = [u64, u32, u32, u32]
+        lib.oracle_check_params.restype = i32
+        lib.oracle_block_index.argtypes = [u64, u64]
+        lib.oracle_block_index.restype = u64
+        lib.oracle_pattern.argtypes = [u64, u32, u32, u32, vp]
+        lib.oracle_pattern.restype = i32
+        lib.oracle_add.argtypes = [vp, u64, u32, u32, u32, u64, vp, u64]
+        lib.oracle_add.restype = i32
+        lib.oracle_contains.argtypes = [vp, u64, u32, u32, u32, u64, vp, u64, vp]
+        lib.oracle_contains.restype = i32
+        lib.oracle_clear.argtypes = [vp, u64]
+        lib.oracle_clear.restype = None
+        lib.oracle_block_words.argtypes = [u64, u32, u32, u32, u64, vp, u64, vp, u64, vp]
+        lib.oracle_block_words.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _keys(keys) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(keys, dtype=np.uint64))
+
+
+def xxh64(data: bytes, seed: int = 0) -> int:
+    buf = np.frombuffer(bytes(data) + b"\0", dtype=np.uint8)
+    return int(_load().oracle_xxh64(_ptr(buf), len(data), seed & (2**64 - 1)))
+
+
+def hash_key(key: int, seed: int = 0) -> int:
+    return int(_load().oracle_hash_key(key & (2**64 - 1), seed & (2**64 - 1)))
+
+
+def salts() -> list[int]:
+    out = np.zeros(MAX_K, dtype=np.uint32)
+    _load().oracle_salts(_ptr(out))
+    return [int(v) for v in out]
+
+
+def check_params(num_blocks: int, words_per_block: int, word_bits: int, k: int) -> bool:
+    if not (0 <= num_blocks < 2**64):
+        return False
+    return _load().oracle_check_params(num_blocks, words_per_block, word_bits, k) == 0
+
+
+def block_index(h: int, num_blocks: int) -> int:
+    return int(_load().oracle_block_index(h, num_blocks))
+
+
+def pattern(h: int, words_per_block: int, word_bits: int, k: int) -> list[int]:
+    out = np.zeros(16, dtype=np.uint64)
+    rc = _load().oracle_pattern(h, words_per_block, word_bits, k, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad filter parameters")
+    return [int(v) for v in out[:words_per_block]]
+
+
+class OracleFilter:
+    """Host-memory filter state driven by the C oracle."""
+
+    def __init__(self, num_blocks: int, words_per_block: int, word_bits: int,
+                 k: int, seed: int = 0):
+        if not check_params(num_blocks, words_per_block, word_bits, k):
+            raise ValueError("bad filter parameters")
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.k = k
+        self.seed = seed & (2**64 - 1)
+        self.nbytes = num_blocks * words_per_block * word_bits // 8
+        self.bytes = np.zeros(self.nbytes, dtype=np.uint8)
+
+    def _args(self):
+        return (self.num_blocks, self.words_per_block, self.word_bits, self.k, self.seed)
+
+    def add(self, keys) -> None:
+        keys = _keys(keys)
+        rc = _load().oracle_add(_ptr(self.bytes), *self._args(), _ptr(keys), keys.size)
+        assert rc == 0
+
+    def contains(self, keys) -> np.ndarray:
+        keys = _keys(keys)
+        out = np.zeros(max(keys.size, 1), dtype=np.uint8)
+        rc = _load().oracle_contains(_ptr(self.bytes), *self._args(), _ptr(keys),
+                                     keys.size, _ptr(out))
+        assert rc == 0
+        return out[: keys.size]
+
+    def clear(self) -> None:
+        _load().oracle_clear(_ptr(self.bytes), self.nbytes)
+
+    def words(self) -> np.ndarray:
+        """The state as little-endian words of ``word_bits`` bits."""
+        dt = np.dtype("<u4") if self.word_bits == 32 else np.dtype("<u8")
+        return self.bytes.view(dt)
+
+
+def block_words(num_blocks: int, words_per_block: int, word_bits: int, k: int,
+                seed: int, keys, blocks) -> np.ndarray:
+    """Bytes of the selected blocks after adding ``keys`` (one row per block)."""
+    keys = _keys(keys)
+    sel = np.ascontiguousarray(np.asarray(blocks, dtype=np.uint64))
+    block_bytes = words_per_block * word_bits // 8
+    out = np.zeros((max(sel.size, 1), block_bytes), dtype=np.uint8)
+    rc = _load().oracle_block_words(num_blocks, words_per_block, word_bits, k,
+                                    seed & (2**64 - 1), _ptr(keys), keys.size,
+                                    _ptr(sel), sel.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad parameters or block selection")
+    return out[: sel.size]

@@ -1,0 +1,287 @@
+/*
+ * bf_oracle.c -- CPU oracle for the blocked / sectorized Bloom filter.
+ *
+ * TEST INFRASTRUCTURE ONLY (see bf_oracle.h).  Plain single-threaded C,
+ * written to be checked against the paper by eye, not to be fast.  Nothing
+ * here is shared with the HIP library.
+ *
+ * Parity pins (tests): XXH64 against the independent python-xxhash library;
+ * filter bits against a brute-force set model on tiny filters; closed-form
+ * false-positive rate and fill fraction; invariants (no false negatives,
+ * order independence, union = OR); special cases of the block rule.
+ */
+#include "bf_oracle.h"
+
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* xxHash64, following the published algorithm description.  The paper uses */
+/* a 64-bit xxHash as the per-key base hash (Sec. IV-B).                     */
+/* ------------------------------------------------------------------------ */
+
+static const uint64_t XXP1 = 0x9E3779B185EBCA87ULL;
+static const uint64_t XXP2 = 0xC2B2AE3D27D4EB4FULL;
+static const uint64_t XXP3 = 0x165667B19E3779F9ULL;
+static const uint64_t XXP4 = 0x85EBCA77C2B2AE63ULL;
+static const uint64_t XXP5 = 0x27D4EB2F165667C5ULL;
+
+static uint64_t rotl64(uint64_t x, unsigned r) {
+    return (x << r) | (x >> (64u - r));
+}
+
+static uint64_t read_le64(const uint8_t *p) {
+    uint64_t v = 0;
+    for (int i = 7; i >= 0; --i) v = (v << 8) | p[i];
+    return v;
+}
+
+static uint32_t read_le32(const uint8_t *p) {
+    uint32_t v = 0;
+    for (int i = 3; i >= 0; --i) v = (v << 8) | p[i];
+    return v;
+}
+
+/* One accumulator step: acc + lane*P2, rotate left 31, times P1. */
+static uint64_t xx_round(uint64_t acc, uint64_t lane) {
+    acc += lane * XXP2;
+    acc = rotl64(acc, 31);
+    return acc * XXP1;
+}
+
+/* Folds one of the four stripe accumulators into the hash. */
+static uint64_t xx_merge(uint64_t h, uint64_t acc) {
+    h ^= xx_round(0, acc);
+    return h * XXP1 + XXP4;
+}
+
+uint64_t oracle_xxh64(const uint8_t *data, size_t len, uint64_t seed) {
+    const uint8_t *p = data;
+    const uint8_t *end = data + len;
+    uint64_t h;
+
+    if (len >= 32) {
+        /* Four parallel accumulators over 32-byte stripes. */
+        uint64_t v1 = seed + XXP1 + XXP2;
+        uint64_t v2 = seed + XXP2;
+        uint64_t v3 = seed;
+        uint64_t v4 = seed - XXP1;
+        while ((size_t)(end - p) >= 32) {
+            v1 = xx_round(v1, read_le64(p));
+            v2 = xx_round(v2, read_le64(p + 8));
+            v3 = xx_round(v3, read_le64(p + 16));
+            v4 = xx_round(v4, read_le64(p + 24));
+            p += 32;
+        }
+        h = rotl64(v1, 1) + rotl64(v2, 7) + rotl64(v3, 12) + rotl64(v4, 18);
+        h = xx_merge(h, v1);
+        h = xx_merge(h, v2);
+        h = xx_merge(h, v3);
+        h = xx_merge(h, v4);
+    } else {
+        h = seed + XXP5;
+    }
+    h += (uint64_t)len;
+
+    /* Remaining whole 8-byte lanes. */
+    while ((size_t)(end - p) >= 8) {
+        h ^= xx_round(0, read_le64(p));
+        h = rotl64(h, 27) * XXP1 + XXP4;
+        p += 8;
+    }
+    /* One remaining 4-byte lane. */
+    if ((size_t)(end - p) >= 4) {
+        h ^= (uint64_t)read_le32(p) * XXP1;
+        h = rotl64(h, 23) * XXP2 + XXP3;
+        p += 4;
+    }
+    /* Remaining single bytes. */
+    while (p < end) {
+        h ^= (uint64_t)(*p) * XXP5;
+        h = rotl64(h, 11) * XXP1;
+        p += 1;
+    }
+    /* Final avalanche. */
+    h ^= h >> 33;
+    h *= XXP2;
+    h ^= h >> 29;
+    h *= XXP3;
+    h ^= h >> 32;
+    return h;
+}
+
+uint64_t oracle_hash_key(uint64_t key, uint64_t seed) {
+    uint8_t bytes[8];
+    for (int i = 0; i < 8; ++i) bytes[i] = (uint8_t)(key >> (8 * i));
+    return oracle_xxh64(bytes, 8, seed);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Salts: k odd multipliers (Sec. IV-B).  The paper does not print values;   */
+/* they are derived from a fixed seed so that any implementation can         */
+/* rebuild them.                                                             */
+/* ------------------------------------------------------------------------ */
+
+void oracle_salts(uint32_t out[ORACLE_MAX_K]) {
+    for (uint32_t j = 0; j < ORACLE_MAX_K; ++j) {
+        uint64_t h = oracle_hash_key((uint64_t)j, ORACLE_SALT_SEED);
+        out[j] = (uint32_t)(h & 0xFFFFFFFFULL) | 1u;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Parameters (Sec. II-A-4: s = B/S words, an SBF needs k >= s).             */
+/* ------------------------------------------------------------------------ */
+
+int oracle_check_params(uint64_t num_blocks, uint32_t words_per_block,
+                        uint32_t word_bits, uint32_t k) {
+    uint32_t s = words_per_block;
+    if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return -1;
+    if (!(word_bits == 32 || word_bits == 64)) return -1;
+    if (k < s || k > ORACLE_MAX_K) return -1;
+    if (num_blocks < 1 || num_blocks > (1ULL << 32)) return -1;
+    return 0;
+}
+
+/* One block per key, chosen uniformly from the upper 32 hash bits
+ * (Sec. II-A-2: an additional hash selects the block). */
+uint64_t oracle_block_index(uint64_t h, uint64_t num_blocks) {
+    uint64_t hi = h >> 32;
+    /* hi < 2^32 and num_blocks <= 2^32, so the product fits in 64 bits. */
+    return (hi * num_blocks) >> 32;
+}
+
+static unsigned log2_word_bits(uint32_t word_bits) {
+    return word_bits == 64 ? 6u : 5u;
+}
+
+/* Pattern: bit j (j = 0..k-1) sits at position p_j of word j mod s, where
+ * p_j is the top log2(S) bits of the 32-bit product lo32(h) * a_j
+ * (Sec. II-A-4 for the word split, Sec. IV-B for the salted products). */
+static void pattern_with_salts(uint64_t h, uint32_t words_per_block,
+                               uint32_t word_bits, uint32_t k,
+                               const uint32_t *salts, uint64_t *patterns) {
+    uint32_t lo = (uint32_t)(h & 0xFFFFFFFFULL);
+    unsigned L = log2_word_bits(word_bits);
+    for (uint32_t w = 0; w < words_per_block; ++w) patterns[w] = 0;
+    for (uint32_t j = 0; j < k; ++j) {
+        uint32_t product = lo * salts[j];          /* mod 2^32 */
+        uint32_t p = product >> (32u - L);         /* in [0, S) */
+        patterns[j % words_per_block] |= 1ULL << p;
+    }
+}
+
+int oracle_pattern(uint64_t h, uint32_t words_per_block, uint32_t word_bits,
+                   uint32_t k, uint64_t *patterns) {
+    if (oracle_check_params(1, words_per_block, word_bits, k) != 0) return -1;
+    uint32_t salts[ORACLE_MAX_K];
+    oracle_salts(salts);
+    pattern_with_salts(h, words_per_block, word_bits, k, salts, patterns);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Filter state as bytes: word (blk, w) at (blk*s + w) * S/8, little-endian. */
+/* ------------------------------------------------------------------------ */
+
+static int get_bit(const uint8_t *words, uint64_t word_index,
+                   uint32_t word_bits, unsigned p) {
+    uint64_t byte = word_index * (word_bits / 8) + p / 8;
+    return (words[byte] >> (p % 8)) & 1;
+}
+
+static void set_bit(uint8_t *words, uint64_t word_index, uint32_t word_bits,
+                    unsigned p) {
+    uint64_t byte = word_index * (word_bits / 8) + p / 8;
+    words[byte] = (uint8_t)(words[byte] | (1u << (p % 8)));
+}
+
+int oracle_add(uint8_t *filter, uint64_t num_blocks, uint32_t words_per_block,
+               uint32_t word_bits, uint32_t k, uint64_t seed,
+               const uint64_t *keys, uint64_t n) {
+    if (oracle_check_params(num_blocks, words_per_block, word_bits, k) != 0)
+        return -1;
+    uint64_t patterns[16];
+    uint32_t salts[ORACLE_MAX_K];
+    oracle_salts(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint64_t blk = oracle_block_index(h, num_blocks);
+        pattern_with_salts(h, words_per_block, word_bits, k, salts, patterns);
+        for (uint32_t w = 0; w < words_per_block; ++w) {
+            for (unsigned p = 0; p < word_bits; ++p) {
+                if ((patterns[w] >> p) & 1ULL)
+                    set_bit(filter, blk * words_per_block + w, word_bits, p);
+            }
+        }
+    }
+    return 0;
+}
+
+int oracle_contains(const uint8_t *filter, uint64_t num_blocks,
+                    uint32_t words_per_block, uint32_t word_bits, uint32_t k,
+                    uint64_t seed, const uint64_t *keys, uint64_t n,
+                    uint8_t *out) {
+    if (oracle_check_params(num_blocks, words_per_block, word_bits, k) != 0)
+        return -1;
+    uint64_t patterns[16];
+    uint32_t salts[ORACLE_MAX_K];
+    oracle_salts(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint64_t blk = oracle_block_index(h, num_blocks);
+        pattern_with_salts(h, words_per_block, word_bits, k, salts, patterns);
+        int all_set = 1;
+        for (uint32_t w = 0; w < words_per_block; ++w) {
+            for (unsigned p = 0; p < word_bits; ++p) {
+                if (((patterns[w] >> p) & 1ULL) &&
+                    !get_bit(filter, blk * words_per_block + w, word_bits, p))
+                    all_set = 0;
+            }
+        }
+        out[i] = (uint8_t)all_set;
+    }
+    return 0;
+}
+
+void oracle_clear(uint8_t *filter, uint64_t nbytes) {
+    for (uint64_t i = 0; i < nbytes; ++i) filter[i] = 0;
+}
+
+int oracle_block_words(uint64_t num_blocks, uint32_t words_per_block,
+                       uint32_t word_bits, uint32_t k, uint64_t seed,
+                       const uint64_t *keys, uint64_t n, const uint64_t *sel,
+                       uint64_t nsel, uint8_t *out) {
+    if (oracle_check_params(num_blocks, words_per_block, word_bits, k) != 0)
+        return -1;
+    /* slot_of[blk] = 1 + position of blk in sel, 0 if blk is not selected. */
+    uint32_t *slot_of = (uint32_t *)calloc(num_blocks, sizeof(uint32_t));
+    if (!slot_of) return -1;
+    for (uint64_t i = 0; i < nsel; ++i) {
+        if (sel[i] >= num_blocks || slot_of[sel[i]] != 0 || nsel >= 0xFFFFFFFFULL) {
+            free(slot_of);
+            return -1;
+        }
+        slot_of[sel[i]] = (uint32_t)(i + 1);
+    }
+    uint64_t block_bytes = (uint64_t)words_per_block * (word_bits / 8);
+    memset(out, 0, nsel * block_bytes);
+    uint64_t patterns[16];
+    uint32_t salts[ORACLE_MAX_K];
+    oracle_salts(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint64_t blk = oracle_block_index(h, num_blocks);
+        uint32_t slot = slot_of[blk];
+        if (slot == 0) continue;
+        pattern_with_salts(h, words_per_block, word_bits, k, salts, patterns);
+        uint8_t *dst = out + (uint64_t)(slot - 1) * block_bytes;
+        for (uint32_t w = 0; w < words_per_block; ++w) {
+            for (unsigned p = 0; p < word_bits; ++p) {
+                if ((patterns[w] >> p) & 1ULL) set_bit(dst, w, word_bits, p);
+            }
+        }
+    }
+    free(slot_of);
+    return 0;
+}
