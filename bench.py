@@ -1,0 +1,351 @@
+#!/usr/bin/env python3
+"""Benchmark: bulk add + bulk contains on a 1 GiB DRAM-resident sectorized
+Bloom filter on one MI355X, against a random-access bound measured on the
+same GPU.
+
+One step = clear the filter, add 2^28 uniform uint64 keys, then look up
+2^28 queries at 0 %, 50 % and 100 % hit ratio (256-bit blocks of 8 x 32-bit
+words, k = 8, 2^25 blocks).  The value is keys processed per second over the
+whole step (adds + lookups), inputs already resident in HBM.
+
+Prints one JSON line (see the module-level contract in the design doc), e.g.
+  python bench.py --steps 20 --warmup 3
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Gkeys/s add+contains, 1 GiB blocked BF, % random-gather bound; p99 served"
+PEAK_HBM_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = ["bf_kernels.hpp", "bf_hash.hpp", "bf_api.hip"]
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_15595_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def parse_mapping(text: str | None):
+    if not text:
+        return None
+    parts = [int(x) for x in text.split(",")]
+    while len(parts) < 5:
+        parts.append(0)
+    return parts
+
+
+class Timer:
+    """HIP events on torch's current stream (the stream the kernels run on)."""
+
+    def __init__(self, torch):
+        self.torch = torch
+        self.start = torch.cuda.Event(enable_timing=True)
+        self.stop = torch.cuda.Event(enable_timing=True)
+
+    def __enter__(self):
+        self.start.record()
+        return self
+
+    def __exit__(self, *exc):
+        self.stop.record()
+
+    def ms(self) -> float:
+        return self.start.elapsed_time(self.stop)
+
+
+def measure_bounds(torch, nbytes: int, seg: int, n_access: int, reps: int = 3) -> dict:
+    """Random-access rates (G accesses/s) over an nbytes buffer."""
+    import ctypes
+
+    from paper_2512_15595_amd import bf as bfmod
+
+    lib = ctypes.CDLL(bfmod.LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    lib.bfb_random_read.argtypes = [vp, u64, u32, u32, u64, u32, vp, vp]
+    lib.bfb_random_atomic_or.argtypes = [vp, u64, u32, u32, u64, u32, vp]
+    lib.bfb_gups.argtypes = [vp, u64, u64, u32, vp]
+    lib.bfb_fill_random_index.argtypes = [vp, u64, u64, u32, vp]
+    lib.bfb_random_read_indexed.argtypes = [vp, u64, u32, vp, u64, vp, vp]
+
+    stream = torch.cuda.current_stream().cuda_stream
+    buf = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    sink = torch.zeros(1, dtype=torch.int32, device="cuda")
+    idx = torch.empty(n_access, dtype=torch.int64, device="cuda")
+    out = torch.empty(n_access, dtype=torch.uint8, device="cuda")
+    rc = lib.bfb_fill_random_index(idx.data_ptr(), n_access, nbytes // seg, 77, stream)
+    assert rc == 0
+
+    def best(fn):
+        rates = []
+        for r in range(reps):
+            with Timer(torch) as t:
+                rc = fn(r)
+            assert rc == 0, rc
+            torch.cuda.synchronize()
+            rates.append(n_access / (t.ms() * 1e-3) / 1e9)
+        return max(rates)
+
+    res = {}
+    for s_bytes, lanes in ((8, 1), (seg, 1), (seg, 2)):
+        res[f"read_{s_bytes}B_x{lanes}"] = best(
+            lambda r, s_bytes=s_bytes, lanes=lanes: lib.bfb_random_read(
+                buf.data_ptr(), nbytes, s_bytes, lanes, n_access, 1000 + r, sink.data_ptr(), stream))
+    res[f"read_{seg}B_indexed"] = best(
+        lambda r: lib.bfb_random_read_indexed(buf.data_ptr(), nbytes, seg, idx.data_ptr(), n_access,
+                                              out.data_ptr(), stream))
+    res["gups_8B"] = best(lambda r: lib.bfb_gups(buf.data_ptr(), nbytes, n_access, 2000 + r, stream))
+    for s_bytes, lanes in ((8, 1), (seg, 1), (seg, seg // 8)):
+        res[f"atomic_or_{s_bytes}B_x{lanes}"] = best(
+            lambda r, s_bytes=s_bytes, lanes=lanes: lib.bfb_random_atomic_or(
+                buf.data_ptr(), nbytes, s_bytes, lanes, n_access, 3000 + r, stream))
+    del buf, idx, out
+    torch.cuda.empty_cache()
+    read_keys = [k for k in res if k.startswith("read_")]
+    write_keys = [k for k in res if k.startswith("atomic_") or k.startswith("gups")]
+    return {
+        "rates_g_per_s": {k: round(v, 3) for k, v in res.items()},
+        "contains_bound": max(res[k] for k in read_keys),
+        "contains_bound_shape": max(read_keys, key=lambda k: res[k]),
+        "add_bound": max(res[k] for k in write_keys),
+        "add_bound_shape": max(write_keys, key=lambda k: res[k]),
+    }
+
+
+def committed_traffic(kernel: str, sample_keys: int):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(PROFILE_DIR, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        data = json.load(fh)
+    if data.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    entry = data.get("kernels", {}).get(kernel)
+    if not entry or entry.get("keys_per_launch") != sample_keys:
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(adds, queries, params, budget_s: float) -> dict:
+    """The CPU oracle (single thread) on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+
+    ref = oracle.OracleFilter(params["num_blocks"], params["words_per_block"],
+                              params["word_bits"], params["k"], params["seed"])
+    # calibrate on a small slice, then size the sample to the time budget
+    probe = 1 << 16
+    t0 = time.perf_counter()
+    ref.add(adds[:probe])
+    ref.contains(queries[:probe])
+    per_key = (time.perf_counter() - t0) / (2 * probe)
+    n = int(min(adds.size, max(probe, budget_s / per_key / 2)))
+    n = 1 << max(16, n.bit_length() - 1)
+    ref.clear()
+    t0 = time.perf_counter()
+    ref.add(adds[:n])
+    t_add = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = ref.contains(queries[:n])
+    t_contains = time.perf_counter() - t0
+    del ref
+    return {
+        "value": round(2 * n / (t_add + t_contains) / 1e9, 6),
+        "unit": "Gkeys/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"{n} adds then {n} lookups (50% hits) on the full 1 GiB filter in host memory; "
+                   f"add {n / t_add / 1e6:.2f} Mkeys/s, contains {n / t_contains / 1e6:.2f} Mkeys/s, "
+                   f"{int(np.sum(r))} positives"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--log2-keys", type=int, default=28)
+    ap.add_argument("--filter-log2-bytes", type=int, default=30)
+    ap.add_argument("--words-per-block", type=int, default=8)
+    ap.add_argument("--word-bits", type=int, default=32)
+    ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--map-add", type=str, default=None, help="theta,phi,kt[,atomic_bits,max_wg]")
+    ap.add_argument("--map-contains", type=str, default=None, help="theta,phi,kt[,0,max_wg]")
+    ap.add_argument("--no-bound", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
+              "multi-GPU path (see the sharding notes in DESIGN.md); use --gpus 1.",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2512_15595_amd import workloads
+    from paper_2512_15595_amd.bf import BF_OP_ADD, BF_OP_CONTAINS, BloomFilter
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    n = 1 << args.log2_keys
+    s, S, k = args.words_per_block, args.word_bits, args.k
+    block_bytes = s * S // 8
+    filter_bytes = 1 << args.filter_log2_bytes
+    num_blocks = filter_bytes // block_bytes
+    params = dict(num_blocks=num_blocks, words_per_block=s, word_bits=S, k=k, seed=0)
+    workload = f"dram_{filter_bytes >> 20}MiB_sbf_{s}x{S}_k{k}"
+    log(f"[bench] workload {workload}: {n} adds, 3 x {n} lookups; generating keys")
+
+    t0 = time.perf_counter()
+    adds, queries = workloads.dram_workload(n)
+    log(f"[bench] keys generated in {time.perf_counter() - t0:.1f}s; uploading")
+    d_adds = torch.from_numpy(adds.view(np.int64)).to("cuda")
+    d_q = {h: torch.from_numpy(q.view(np.int64)).to("cuda") for h, q in queries.items()}
+    d_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+
+    bounds = None
+    if not args.no_bound:
+        log("[bench] measuring the random-access bound on a 1 GiB buffer")
+        bounds = measure_bounds(torch, filter_bytes, block_bytes, n)
+        log(f"[bench] bounds: {bounds}")
+
+    f = BloomFilter(num_blocks, s, S, k, 0)
+    ma, mc = parse_mapping(args.map_add), parse_mapping(args.map_contains)
+    if ma:
+        f.set_mapping(BF_OP_ADD, *ma)
+    if mc:
+        f.set_mapping(BF_OP_CONTAINS, *mc)
+    info = f.info()
+    mapping = {"add": info.mapping[BF_OP_ADD].as_dict(),
+               "contains": info.mapping[BF_OP_CONTAINS].as_dict()}
+
+    times = {"clear": [], "add": [], "contains": []}
+
+    def step(record: bool):
+        tc, ta = Timer(torch), Timer(torch)
+        with tc:
+            f.clear()
+        with ta:
+            f.add(d_adds)
+        tq = []
+        for h in (0, 50, 100):
+            t = Timer(torch)
+            with t:
+                f.contains(d_q[h], out=d_out)
+            tq.append(t)
+        if record:
+            times["clear"].append(tc)
+            times["add"].append(ta)
+            times["contains"].extend(tq)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    log(f"[bench] warmup done ({args.warmup} steps); timing {args.steps} steps")
+    whole_start, whole_stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    whole_start.record()
+    for _ in range(args.steps):
+        step(True)
+    whole_stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = whole_start.elapsed_time(whole_stop)
+
+    # check the last step's results: 100 % hits must all be found
+    f.contains(d_q[100], out=d_out)
+    found = int(d_out.sum().item())
+    f.contains(d_q[0], out=d_out)
+    fp = int(d_out.sum().item())
+    torch.cuda.synchronize()
+    assert found == n, f"false negatives: {n - found}"
+
+    ms = {key: float(np.mean([t.ms() for t in v])) for key, v in times.items()}
+    keys_per_step = 4 * n
+    ms_per_step = total_ms / args.steps
+    value = keys_per_step / (ms_per_step * 1e-3) / 1e9
+    add_rate = n / (ms["add"] * 1e-3) / 1e9
+    contains_rate = n / (ms["contains"] * 1e-3) / 1e9
+
+    # dominant kernel = the op with the larger share of a step
+    add_share, contains_share = ms["add"], 3 * ms["contains"]
+    if add_share >= contains_share:
+        dom, per_key, dom_ms = "add", 8 + 2 * block_bytes, ms["add"]
+    else:
+        dom, per_key, dom_ms = "contains", 8 + block_bytes + 1, ms["contains"]
+    achieved = per_key * n / (dom_ms * 1e-3) / 1e9
+    traffic = committed_traffic(dom, n)
+    roofline = {"bound": "hbm", "kernel": f"bf_{dom}_kernel", "achieved": round(achieved, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_key": per_key,
+                "avg_launch_ms": round(dom_ms, 4)}
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {
+            "workload": workload,
+            "filter_bytes": filter_bytes, "num_blocks": num_blocks, "words_per_block": s,
+            "word_bits": S, "k": k, "adds_per_step": n, "lookups_per_step": 3 * n,
+            "hit_ratios_pct": [0, 50, 100], "mapping": mapping,
+        },
+        "add_gkeys_s": round(add_rate, 3),
+        "contains_gkeys_s": round(contains_rate, 3),
+        "ms": {key: round(v, 4) for key, v in ms.items()},
+        "false_positive_rate_0pct_hits": fp / n,
+        "wall_s_timed": round(wall, 3),
+        "roofline": roofline,
+    }
+    if bounds:
+        result["random_access_bound"] = bounds
+        result["pct_of_bound"] = {
+            "add": round(100 * add_rate / bounds["add_bound"], 2),
+            "contains": round(100 * contains_rate / bounds["contains_bound"], 2),
+        }
+    f.close()
+    del d_adds, d_q, d_out
+    torch.cuda.empty_cache()
+
+    if not args.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        result["cpu_baseline"] = cpu_baseline(adds, queries[50], params, args.cpu_budget_s)
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

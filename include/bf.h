@@ -1,0 +1,145 @@
+/*
+ * bf.h -- C ABI of the MI355X (gfx950) blocked / sectorized Bloom filter.
+ *
+ * The operations are those of the paper "Optimizing Bloom Filters on Modern
+ * GPUs" (arXiv 2512.15595): bulk construction and bulk lookup of an
+ * approximate-membership filter that never reports a false negative
+ * (Sec. I, Sec. II-A-1), in the sectorized layout of Sec. II-A-4 (a block of
+ * s contiguous S-bit words, one block per key, k pattern bits spread over
+ * the words), with the per-key pattern generation of Sec. IV-B and the
+ * tunable execution mapping of Sec. IV-A / IV-C.
+ *
+ * Definition computed (exactly; OR is commutative and idempotent, so every
+ * execution order gives the same words):
+ *   h      = xxHash64 of the key's 8 little-endian bytes with the filter seed;
+ *   blk    = floor(hi32(h) * num_blocks / 2^32);
+ *   a_j    = (xxHash64(LE64(j), 0x73746c61732d6662) mod 2^32) | 1, j < 32;
+ *   bit j  = top log2(S) bits of (lo32(h) * a_j mod 2^32), in word j mod s,
+ *            for j = 0..k-1;
+ *   add      : word (blk, w) |= pattern word w, for all w;
+ *   contains : 1 iff (word & pattern) == pattern for all w of the block.
+ * Word (blk, w) lives at byte offset (blk*s + w) * S/8, little-endian.
+ *
+ * Conventions for every call:
+ *   - Device pointers are plain HIP device addresses (e.g. a torch tensor's
+ *     data_ptr); the caller owns them and keeps them alive until the stream
+ *     has run the work.  Keys are 8-byte aligned uint64 values; results are
+ *     one byte (0 or 1) per key.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls enqueue and return; they never synchronize, except bf_create
+ *     (which zeroes the new words) and bf_destroy (which frees them).
+ *   - Arguments are validated before anything is enqueued; on error nothing
+ *     is enqueued and the status says why.  Launch failures are BF_EDEVICE.
+ *     Faults inside a kernel surface at the caller's next synchronization.
+ *   - Concurrency: bf_add calls on one filter from several streams commute.
+ *     A bf_contains that is not ordered after a bf_add (by stream order or
+ *     events) sees some state between "before" and "after" that add.
+ */
+#ifndef BF_H
+#define BF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bf_status;
+#define BF_OK 0
+#define BF_EINVAL (-1)        /* bad argument: nothing enqueued */
+#define BF_ENOMEM (-2)        /* device allocation failed */
+#define BF_EDEVICE (-3)       /* HIP runtime / launch error */
+#define BF_EUNSUPPORTED (-4)  /* valid request this build has no kernel for */
+
+#define BF_OP_ADD 0
+#define BF_OP_CONTAINS 1
+
+typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
+
+/* Execution mapping of one operation (Sec. IV-A and IV-C).  A field left 0
+ * means "use the default for this layout".
+ *   lanes_per_key   Theta: lanes cooperating on one key, power of two <= 16;
+ *   words_per_lane  Phi:   contiguous words per lane per step, power of two,
+ *                          with Theta * Phi <= words_per_block;
+ *   keys_per_lane   keys loaded and hashed per lane: 1, 2 or 4;
+ *   atomic_bits     add only, 32-bit words only: 64 merges two adjacent
+ *                   words into one 64-bit atomic OR (needs Phi >= 2); 32 or
+ *                   0 otherwise;
+ *   max_workgroups  grid cap of the grid-stride launch (0 = one workgroup
+ *                   per 256 * keys_per_lane keys). */
+typedef struct {
+  uint32_t lanes_per_key;
+  uint32_t words_per_lane;
+  uint32_t keys_per_lane;
+  uint32_t atomic_bits;
+  uint32_t max_workgroups;
+} bf_mapping_t;
+
+typedef struct {
+  uint64_t num_blocks;
+  uint32_t words_per_block;
+  uint32_t word_bits;
+  uint32_t k;
+  int32_t device;          /* HIP device the words live on */
+  uint64_t seed;
+  uint64_t size_bytes;     /* num_blocks * words_per_block * word_bits / 8 */
+  void *d_words;           /* device address of the words (owned by the filter) */
+  bf_mapping_t mapping[2]; /* resolved mapping per op, indexed by BF_OP_* */
+} bf_info_t;
+
+/* Creates a filter on the current HIP device with all words zero.
+ * num_blocks in [1, 2^32]; words_per_block in {1,2,4,8,16}; word_bits in
+ * {32, 64}; words_per_block <= k <= 32 (a sectorized block needs at least
+ * one bit per word, Sec. II-A-5).  Allocates num_blocks * words_per_block *
+ * word_bits / 8 bytes with hipMalloc and zeroes them (synchronously).
+ * *out receives the handle (unchanged on error). */
+bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block,
+                    uint32_t word_bits, uint32_t k, uint64_t seed,
+                    bf_filter **out);
+
+/* Frees the words (after a device synchronization) and the handle.
+ * NULL is accepted and ignored. */
+bf_status bf_destroy(bf_filter *f);
+
+/* Bulk construction: adds keys[0..n) (device pointer).  n = 0 is a no-op.
+ * keys must be non-NULL when n > 0 and 8-byte aligned. */
+bf_status bf_add(bf_filter *f, const uint64_t *d_keys, uint64_t n, void *stream);
+
+/* Bulk lookup: d_out[i] = 1 if keys[i] may be in the filter, 0 if it is
+ * certainly absent (Sec. II-A-1).  d_out is a device array of n bytes. */
+bf_status bf_contains(const bf_filter *f, const uint64_t *d_keys, uint64_t n,
+                      uint8_t *d_out, void *stream);
+
+/* Sets every word to zero (a fill kernel on `stream`). */
+bf_status bf_clear(bf_filter *f, void *stream);
+
+/* Copies the filter words (size_bytes, layout as above) to `dst`, which
+ * may be device or host memory of at least size_bytes bytes; asynchronous on
+ * `stream` (host destinations should be pinned for true asynchrony).  With
+ * bf_import_words this is the save / restore path of a filter. */
+bf_status bf_export_words(const bf_filter *f, void *dst, uint64_t nbytes, void *stream);
+
+/* Overwrites the filter words from `src` (device or host, nbytes must equal
+ * size_bytes), asynchronous on `stream`. */
+bf_status bf_import_words(bf_filter *f, const void *src, uint64_t nbytes, void *stream);
+
+/* Parameters, size, word address and resolved mappings. */
+bf_status bf_info(const bf_filter *f, bf_info_t *out);
+
+/* Selects the execution mapping of one operation; results do not depend on
+ * it.  lanes_per_key = words_per_lane = keys_per_lane = 0 restores the
+ * default.  Invalid combinations give BF_EINVAL. */
+bf_status bf_set_mapping(bf_filter *f, int op, uint32_t lanes_per_key,
+                         uint32_t words_per_lane, uint32_t keys_per_lane);
+
+/* Full form of bf_set_mapping (all fields of bf_mapping_t). */
+bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
+
+/* Static description of a status code. */
+const char *bf_strerror(bf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BF_H */

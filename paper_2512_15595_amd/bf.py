@@ -1,0 +1,246 @@
+"""Thin Python binding of the C ABI in include/bf.h (argument marshalling only).
+
+Low-level functions carry the C names and take plain integers for device
+pointers and streams; every step of add / contains / clear runs in the HIP
+kernels of libbf.so.  ``BloomFilter`` wraps them for torch tensors, taking
+device memory and the current stream from torch and nothing else.
+
+Importing this module loads libbf.so and raises ImportError if it has not
+been built (``python -m paper_2512_15595_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbf.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build the HIP library first "
+        "(python -m paper_2512_15595_amd.build)"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BF_OK = 0
+BF_EINVAL = -1
+BF_ENOMEM = -2
+BF_EDEVICE = -3
+BF_EUNSUPPORTED = -4
+BF_OP_ADD = 0
+BF_OP_CONTAINS = 1
+
+
+class bf_mapping_t(ctypes.Structure):
+    _fields_ = [
+        ("lanes_per_key", ctypes.c_uint32),
+        ("words_per_lane", ctypes.c_uint32),
+        ("keys_per_lane", ctypes.c_uint32),
+        ("atomic_bits", ctypes.c_uint32),
+        ("max_workgroups", ctypes.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+class bf_info_t(ctypes.Structure):
+    _fields_ = [
+        ("num_blocks", ctypes.c_uint64),
+        ("words_per_block", ctypes.c_uint32),
+        ("word_bits", ctypes.c_uint32),
+        ("k", ctypes.c_uint32),
+        ("device", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("size_bytes", ctypes.c_uint64),
+        ("d_words", ctypes.c_void_p),
+        ("mapping", bf_mapping_t * 2),
+    ]
+
+
+_u64, _u32, _i32, _vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p
+_lib.bf_create.argtypes = [_u64, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create.restype = _i32
+_lib.bf_destroy.argtypes = [_vp]
+_lib.bf_destroy.restype = _i32
+_lib.bf_add.argtypes = [_vp, _vp, _u64, _vp]
+_lib.bf_add.restype = _i32
+_lib.bf_contains.argtypes = [_vp, _vp, _u64, _vp, _vp]
+_lib.bf_contains.restype = _i32
+_lib.bf_clear.argtypes = [_vp, _vp]
+_lib.bf_clear.restype = _i32
+_lib.bf_info.argtypes = [_vp, ctypes.POINTER(bf_info_t)]
+_lib.bf_info.restype = _i32
+_lib.bf_set_mapping.argtypes = [_vp, ctypes.c_int, _u32, _u32, _u32]
+_lib.bf_set_mapping.restype = _i32
+_lib.bf_set_mapping_ex.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(bf_mapping_t)]
+_lib.bf_set_mapping_ex.restype = _i32
+_lib.bf_export_words.argtypes = [_vp, _vp, _u64, _vp]
+_lib.bf_export_words.restype = _i32
+_lib.bf_import_words.argtypes = [_vp, _vp, _u64, _vp]
+_lib.bf_import_words.restype = _i32
+_lib.bf_strerror.argtypes = [_i32]
+_lib.bf_strerror.restype = ctypes.c_char_p
+
+
+class BfError(RuntimeError):
+    def __init__(self, status: int, what: str = ""):
+        self.status = status
+        super().__init__(f"{what}: {bf_strerror(status)} ({status})" if what else bf_strerror(status))
+
+
+def _check(status: int, what: str) -> None:
+    if status != BF_OK:
+        raise BfError(status, what)
+
+
+# ---- C names, plain integers -------------------------------------------------
+
+def bf_create(num_blocks: int, words_per_block: int, word_bits: int, k: int, seed: int):
+    """Returns (status, handle)."""
+    h = _vp()
+    st = _lib.bf_create(num_blocks, words_per_block, word_bits, k, seed & (2**64 - 1),
+                        ctypes.byref(h))
+    return st, h
+
+
+def bf_destroy(f) -> int:
+    return _lib.bf_destroy(f)
+
+
+def bf_add(f, d_keys: int, n: int, stream: int = 0) -> int:
+    return _lib.bf_add(f, d_keys, n, stream)
+
+
+def bf_contains(f, d_keys: int, n: int, d_out: int, stream: int = 0) -> int:
+    return _lib.bf_contains(f, d_keys, n, d_out, stream)
+
+
+def bf_clear(f, stream: int = 0) -> int:
+    return _lib.bf_clear(f, stream)
+
+
+def bf_info(f):
+    """Returns (status, bf_info_t)."""
+    info = bf_info_t()
+    st = _lib.bf_info(f, ctypes.byref(info))
+    return st, info
+
+
+def bf_set_mapping(f, op: int, lanes_per_key: int, words_per_lane: int, keys_per_lane: int) -> int:
+    return _lib.bf_set_mapping(f, op, lanes_per_key, words_per_lane, keys_per_lane)
+
+
+def bf_set_mapping_ex(f, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
+                      keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0) -> int:
+    m = bf_mapping_t(lanes_per_key, words_per_lane, keys_per_lane, atomic_bits, max_workgroups)
+    return _lib.bf_set_mapping_ex(f, op, ctypes.byref(m))
+
+
+def bf_export_words(f, dst: int, nbytes: int, stream: int = 0) -> int:
+    return _lib.bf_export_words(f, dst, nbytes, stream)
+
+
+def bf_import_words(f, src: int, nbytes: int, stream: int = 0) -> int:
+    return _lib.bf_import_words(f, src, nbytes, stream)
+
+
+def bf_strerror(status: int) -> str:
+    return _lib.bf_strerror(status).decode()
+
+
+# ---- torch convenience wrapper ----------------------------------------------
+
+def _stream_ptr(stream) -> int:
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+class BloomFilter:
+    """A device-resident filter; keys and results are torch tensors on the GPU."""
+
+    def __init__(self, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
+                 k: int = 8, seed: int = 0):
+        st, h = bf_create(num_blocks, words_per_block, word_bits, k, seed)
+        _check(st, "bf_create")
+        self._h = h
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.k = k
+        self.seed = seed
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self) -> None:
+        if self._h:
+            _check(bf_destroy(self._h), "bf_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _keys(self, keys):
+        import torch
+
+        if keys.dtype not in (torch.uint64, torch.int64) or not keys.is_cuda or not keys.is_contiguous():
+            raise ValueError("keys must be a contiguous uint64/int64 CUDA tensor")
+        return keys
+
+    def add(self, keys, stream=None) -> None:
+        keys = self._keys(keys)
+        _check(bf_add(self._h, keys.data_ptr(), keys.numel(), _stream_ptr(stream)), "bf_add")
+
+    def contains(self, keys, out=None, stream=None):
+        import torch
+
+        keys = self._keys(keys)
+        if out is None:
+            out = torch.empty(keys.numel(), dtype=torch.uint8, device=keys.device)
+        if out.numel() < keys.numel() or out.dtype not in (torch.uint8, torch.bool) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous uint8/bool tensor with one byte per key")
+        _check(bf_contains(self._h, keys.data_ptr(), keys.numel(), out.data_ptr(),
+                           _stream_ptr(stream)), "bf_contains")
+        return out
+
+    def clear(self, stream=None) -> None:
+        _check(bf_clear(self._h, _stream_ptr(stream)), "bf_clear")
+
+    def info(self) -> bf_info_t:
+        st, info = bf_info(self._h)
+        _check(st, "bf_info")
+        return info
+
+    def set_mapping(self, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
+                    keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0) -> None:
+        _check(bf_set_mapping_ex(self._h, op, lanes_per_key, words_per_lane, keys_per_lane,
+                                 atomic_bits, max_workgroups), "bf_set_mapping_ex")
+
+    def words(self, stream=None):
+        """A device copy of the words as a torch uint8 tensor."""
+        import torch
+
+        out = torch.empty(self.size_bytes(), dtype=torch.uint8, device="cuda")
+        _check(bf_export_words(self._h, out.data_ptr(), out.numel(), _stream_ptr(stream)),
+               "bf_export_words")
+        return out
+
+    def load_words(self, src, stream=None) -> None:
+        """Overwrites the words from a uint8 tensor of size_bytes bytes."""
+        if not src.is_contiguous() or src.numel() * src.element_size() != self.size_bytes():
+            raise ValueError("src must be contiguous and exactly size_bytes long")
+        _check(bf_import_words(self._h, src.data_ptr(), self.size_bytes(), _stream_ptr(stream)),
+               "bf_import_words")
+
+    def size_bytes(self) -> int:
+        return self.num_blocks * self.words_per_block * self.word_bits // 8

@@ -1,0 +1,327 @@
+// bf_api.hip -- the C ABI declared in include/bf.h: handle, validation,
+// mapping selection and kernel launch.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <new>
+
+#include "../../include/bf.h"
+#include "bf_hash.hpp"
+#include "bf_kernels.hpp"
+#include "bf_registry.hpp"
+
+namespace bfhip {
+
+Registry& registry() {
+  static Registry r{};
+  return r;
+}
+
+namespace {
+
+std::once_flag g_registry_once;
+
+void init_registry() {
+  std::call_once(g_registry_once, [] {
+    Registry& r = registry();
+    register_u32_s1(r);
+    register_u32_s2(r);
+    register_u32_s4(r);
+    register_u32_s8(r);
+    register_u32_s16(r);
+    register_u64_s1(r);
+    register_u64_s2(r);
+    register_u64_s4(r);
+    register_u64_s8(r);
+    register_u64_s16(r);
+  });
+}
+
+// Zero fill with 16-byte stores (a kernel rather than hipMemsetAsync so a
+// captured graph holds no memset node).
+__global__ __launch_bounds__(256) void clear_kernel(uint8_t* p, uint64_t nbytes) {
+  const uint64_t nvec = nbytes / 16;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  u32x4* q = reinterpret_cast<u32x4*>(p);
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < nvec;
+       i += stride)
+    q[i] = u32x4{0u, 0u, 0u, 0u};
+  // tail (< 16 bytes; the words are 4-byte multiples)
+  const uint64_t tail = nvec * 16;
+  const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (tail + 4 * t < nbytes && t < 4) reinterpret_cast<uint32_t*>(p + tail)[t] = 0u;
+}
+
+bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+}  // namespace bfhip
+
+using namespace bfhip;
+
+struct bf_filter {
+  uint64_t num_blocks;
+  uint32_t s;
+  uint32_t word_bits;
+  uint32_t k;
+  int32_t device;
+  uint64_t seed;
+  uint64_t nbytes;
+  void* d_words;
+  bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
+};
+
+namespace {
+
+bf_mapping_t default_mapping(const bf_filter* f, int op) {
+  bf_mapping_t m{};
+  const uint32_t block_bits = f->s * f->word_bits;
+  if (op == BF_OP_CONTAINS) {
+    // One lane per 256-bit slice of the block, whole slice per lane.
+    m.lanes_per_key = block_bits > 256 ? block_bits / 256 : 1;
+    m.words_per_lane = f->s / m.lanes_per_key;
+    m.keys_per_lane = 2;
+    m.atomic_bits = 0;
+  } else {
+    // One 64-bit atomic per lane, the group covering the block.
+    m.lanes_per_key = block_bits >= 64 ? block_bits / 64 : 1;
+    if (m.lanes_per_key > 16) m.lanes_per_key = 16;
+    m.words_per_lane = f->s / m.lanes_per_key;
+    m.keys_per_lane = 1;
+    m.atomic_bits = (f->word_bits == 32 && m.words_per_lane >= 2) ? 64 : 32;
+  }
+  m.max_workgroups = 0;
+  return m;
+}
+
+bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
+  bf_mapping_t m = f->mapping[op];
+  if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
+    const uint32_t cap = m.max_workgroups;
+    const uint32_t ab = m.atomic_bits;
+    m = default_mapping(f, op);
+    m.max_workgroups = cap;
+    if (ab != 0 && op == BF_OP_ADD && f->word_bits == 32 && m.words_per_lane >= 2) m.atomic_bits = ab;
+  }
+  if (m.atomic_bits == 0) m.atomic_bits = 32;
+  if (k_index(f->k) == 0) {
+    m.lanes_per_key = 1;
+    m.words_per_lane = f->s;
+    m.keys_per_lane = 1;
+    if (!(f->word_bits == 32 && f->s >= 2)) m.atomic_bits = 32;
+  }
+  if (op == BF_OP_CONTAINS) m.atomic_bits = 0;
+  return m;
+}
+
+bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
+  if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
+    // default mapping; only the atomic width may be forced
+    if (m.atomic_bits != 0 && m.atomic_bits != 32 && m.atomic_bits != 64) return BF_EINVAL;
+    return BF_OK;
+  }
+  if (!is_pow2(m.lanes_per_key) || !is_pow2(m.words_per_lane)) return BF_EINVAL;
+  if (m.lanes_per_key > 16) return BF_EINVAL;
+  if (static_cast<uint64_t>(m.lanes_per_key) * m.words_per_lane > f->s) return BF_EINVAL;
+  if (!(m.keys_per_lane == 1 || m.keys_per_lane == 2 || m.keys_per_lane == 4)) return BF_EINVAL;
+  if (op == BF_OP_ADD) {
+    if (!(m.atomic_bits == 0 || m.atomic_bits == 32 || m.atomic_bits == 64)) return BF_EINVAL;
+    if (m.atomic_bits == 64 && !(f->word_bits == 32 && m.words_per_lane >= 2)) return BF_EINVAL;
+  } else if (m.atomic_bits != 0) {
+    return BF_EINVAL;
+  }
+  return BF_OK;
+}
+
+bf_status launch(const bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
+                 void* stream) {
+  init_registry();
+  bf_mapping_t m = resolve_mapping(f, op);
+  // Keys per lane needs 8*KT-byte aligned keys (and KT-byte aligned results);
+  // fall back to fewer keys per lane otherwise.
+  uint32_t kt = m.keys_per_lane;
+  while (kt > 1 && ((reinterpret_cast<uintptr_t>(keys) % (8u * kt)) != 0 ||
+                    (out != nullptr && reinterpret_cast<uintptr_t>(out) % kt != 0)))
+    kt >>= 1;
+  int atom64 = (op == BF_OP_ADD && m.atomic_bits == 64) ? 1 : 0;
+  const int kidx = k_index(f->k);
+  if (kidx == 0) {
+    // k without compiled variants: one lane per key, one key per lane.
+    m.lanes_per_key = 1;
+    m.words_per_lane = f->s;
+    kt = 1;
+    if (atom64 && !(f->word_bits == 32 && f->s >= 2)) atom64 = 0;
+  }
+  const void* fn = registry().fn[registry_index(op, static_cast<int>(f->word_bits),
+                                                static_cast<int>(f->s), kidx,
+                                                static_cast<int>(m.lanes_per_key),
+                                                static_cast<int>(m.words_per_lane),
+                                                static_cast<int>(kt), atom64)];
+  if (fn == nullptr) return BF_EUNSUPPORTED;
+
+  const uint64_t tile = static_cast<uint64_t>(kBlockThreads) * kt;
+  const uint64_t ntiles = (n + tile - 1) / tile;
+  uint64_t grid = ntiles;
+  const uint64_t hard_cap = 1ull << 22;  // keeps grid * 256 below 2^32
+  if (grid > hard_cap) grid = hard_cap;
+  if (m.max_workgroups != 0 && grid > m.max_workgroups) grid = m.max_workgroups;
+
+  BfArgs a{};
+  a.words = f->d_words;
+  a.keys = keys;
+  a.out = out;
+  a.n = n;
+  a.hash_init = xxh64_u64_init(f->seed);
+  a.nb_lo = static_cast<uint32_t>(f->num_blocks);
+  a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
+  a.k = f->k;
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<uint32_t>(grid)), dim3(kBlockThreads), args,
+                                 0, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return BF_EDEVICE;
+  return BF_OK;
+}
+
+bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
+  uint64_t nvec = nbytes / 16;
+  uint64_t grid = (nvec + 255) / 256;
+  if (grid < 1) grid = 1;
+  if (grid > 65536) grid = 65536;
+  hipLaunchKernelGGL(clear_kernel, dim3(static_cast<uint32_t>(grid)), dim3(256), 0, stream,
+                     static_cast<uint8_t*>(p), nbytes);
+  return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits, uint32_t k,
+                    uint64_t seed, bf_filter** out) {
+  if (out == nullptr) return BF_EINVAL;
+  const uint32_t s = words_per_block;
+  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
+  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
+  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
+  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
+
+  bf_filter* f = new (std::nothrow) bf_filter{};
+  if (f == nullptr) return BF_ENOMEM;
+  f->num_blocks = num_blocks;
+  f->s = s;
+  f->word_bits = word_bits;
+  f->k = k;
+  f->seed = seed;
+  f->nbytes = num_blocks * s * (word_bits / 8);
+  if (hipGetDevice(&f->device) != hipSuccess) {
+    delete f;
+    return BF_EDEVICE;
+  }
+  if (hipMalloc(&f->d_words, f->nbytes) != hipSuccess) {
+    (void)hipGetLastError();
+    delete f;
+    return BF_ENOMEM;
+  }
+  if (clear_words(f->d_words, f->nbytes, nullptr) != BF_OK ||
+      hipStreamSynchronize(nullptr) != hipSuccess) {
+    (void)hipFree(f->d_words);
+    delete f;
+    return BF_EDEVICE;
+  }
+  *out = f;
+  return BF_OK;
+}
+
+bf_status bf_destroy(bf_filter* f) {
+  if (f == nullptr) return BF_OK;
+  bf_status st = BF_OK;
+  if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
+  if (hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
+  delete f;
+  return st;
+}
+
+bf_status bf_add(bf_filter* f, const uint64_t* d_keys, uint64_t n, void* stream) {
+  if (f == nullptr) return BF_EINVAL;
+  if (n == 0) return BF_OK;
+  if (d_keys == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0) return BF_EINVAL;
+  return launch(f, BF_OP_ADD, d_keys, n, nullptr, stream);
+}
+
+bf_status bf_contains(const bf_filter* f, const uint64_t* d_keys, uint64_t n, uint8_t* d_out,
+                      void* stream) {
+  if (f == nullptr) return BF_EINVAL;
+  if (n == 0) return BF_OK;
+  if (d_keys == nullptr || d_out == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0)
+    return BF_EINVAL;
+  return launch(f, BF_OP_CONTAINS, d_keys, n, d_out, stream);
+}
+
+bf_status bf_clear(bf_filter* f, void* stream) {
+  if (f == nullptr) return BF_EINVAL;
+  return clear_words(f->d_words, f->nbytes, static_cast<hipStream_t>(stream));
+}
+
+bf_status bf_export_words(const bf_filter* f, void* dst, uint64_t nbytes, void* stream) {
+  if (f == nullptr || dst == nullptr || nbytes < f->nbytes) return BF_EINVAL;
+  if (hipMemcpyAsync(dst, f->d_words, f->nbytes, hipMemcpyDefault,
+                     static_cast<hipStream_t>(stream)) != hipSuccess)
+    return BF_EDEVICE;
+  return BF_OK;
+}
+
+bf_status bf_import_words(bf_filter* f, const void* src, uint64_t nbytes, void* stream) {
+  if (f == nullptr || src == nullptr || nbytes != f->nbytes) return BF_EINVAL;
+  if (hipMemcpyAsync(f->d_words, src, f->nbytes, hipMemcpyDefault,
+                     static_cast<hipStream_t>(stream)) != hipSuccess)
+    return BF_EDEVICE;
+  return BF_OK;
+}
+
+bf_status bf_info(const bf_filter* f, bf_info_t* out) {
+  if (f == nullptr || out == nullptr) return BF_EINVAL;
+  bf_info_t i{};
+  i.num_blocks = f->num_blocks;
+  i.words_per_block = f->s;
+  i.word_bits = f->word_bits;
+  i.k = f->k;
+  i.device = f->device;
+  i.seed = f->seed;
+  i.size_bytes = f->nbytes;
+  i.d_words = f->d_words;
+  i.mapping[BF_OP_ADD] = resolve_mapping(f, BF_OP_ADD);
+  i.mapping[BF_OP_CONTAINS] = resolve_mapping(f, BF_OP_CONTAINS);
+  *out = i;
+  return BF_OK;
+}
+
+bf_status bf_set_mapping_ex(bf_filter* f, int op, const bf_mapping_t* m) {
+  if (f == nullptr || m == nullptr) return BF_EINVAL;
+  if (op != BF_OP_ADD && op != BF_OP_CONTAINS) return BF_EINVAL;
+  bf_status st = validate_mapping(f, op, *m);
+  if (st != BF_OK) return st;
+  f->mapping[op] = *m;
+  return BF_OK;
+}
+
+bf_status bf_set_mapping(bf_filter* f, int op, uint32_t lanes_per_key, uint32_t words_per_lane,
+                         uint32_t keys_per_lane) {
+  bf_mapping_t m{};
+  m.lanes_per_key = lanes_per_key;
+  m.words_per_lane = words_per_lane;
+  m.keys_per_lane = keys_per_lane;
+  return bf_set_mapping_ex(f, op, &m);
+}
+
+const char* bf_strerror(bf_status s) {
+  switch (s) {
+    case BF_OK: return "ok";
+    case BF_EINVAL: return "invalid argument";
+    case BF_ENOMEM: return "device allocation failed";
+    case BF_EDEVICE: return "HIP runtime or launch error";
+    case BF_EUNSUPPORTED: return "no kernel for this layout and mapping";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"
