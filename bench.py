@@ -128,6 +128,27 @@ def measure_bounds(torch, nbytes: int, seg: int, n_access: int, reps: int = 3) -
     }
 
 
+def streaming_copy(torch, nbytes: int) -> float:
+    """One streaming copy of nbytes (the byte-counter calibration kernel);
+    returns read+write GB/s of the last of three runs."""
+    import ctypes
+
+    from paper_2512_15595_amd import bf as bfmod
+
+    lib = ctypes.CDLL(bfmod.LIB_PATH)
+    lib.bfb_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    for _ in range(3):
+        with Timer(torch) as t:
+            assert lib.bfb_copy(dst.data_ptr(), src.data_ptr(), nbytes, stream) == 0
+        torch.cuda.synchronize()
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (t.ms() * 1e-3) / 1e9
+
+
 def committed_traffic(kernel: str, sample_keys: int):
     """HBM bytes per launch from a committed rocprofv3 counter summary, if it
     was taken on the current kernel sources; else None."""
@@ -194,6 +215,8 @@ def main() -> int:
     ap.add_argument("--no-bound", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB streaming copy (byte-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -231,6 +254,11 @@ def main() -> int:
         log("[bench] measuring the random-access bound on a 1 GiB buffer")
         bounds = measure_bounds(torch, filter_bytes, block_bytes, n)
         log(f"[bench] bounds: {bounds}")
+
+    copy_gbs = None
+    if args.calibrate_copy:
+        copy_gbs = streaming_copy(torch, 1 << 30)
+        log(f"[bench] streaming copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
 
     f = BloomFilter(num_blocks, s, S, k, 0)
     ma, mc = parse_mapping(args.map_add), parse_mapping(args.map_contains)
@@ -330,6 +358,8 @@ def main() -> int:
         "wall_s_timed": round(wall, 3),
         "roofline": roofline,
     }
+    if copy_gbs is not None:
+        result["copy_1GiB_gbs"] = round(copy_gbs, 1)
     if bounds:
         result["random_access_bound"] = bounds
         result["pct_of_bound"] = {
