@@ -37,6 +37,13 @@ int bfb_random_read(const void *d_buf, uint64_t buf_bytes, uint32_t seg_bytes,
                     uint32_t lanes_per_seg, uint64_t n_access, uint32_t seed,
                     uint32_t *d_sink, void *stream);
 
+/* As bfb_random_read with one lane per segment (seg_bytes 32 or 128), each
+ * 16-byte load issued with a cache policy: 1 = nontemporal hint, 2 = sc1,
+ * 3 = sc0 sc1, 4 = nt sc1 (gfx950 cache-coherence / temporal bits). */
+int bfb_random_read_policy(const void *d_buf, uint64_t buf_bytes, uint32_t seg_bytes,
+                           uint32_t policy, uint64_t n_access, uint32_t seed,
+                           uint32_t *d_sink, void *stream);
+
 /* Writes n uniform random segment indices in [0, nseg) (nseg <= 2^32). */
 int bfb_fill_random_index(uint64_t *d_idx, uint64_t n, uint64_t nseg, uint32_t seed,
                           void *stream);

@@ -81,6 +81,28 @@ _lib.bf_export_words.argtypes = [_vp, _vp, _u64, _vp]
 _lib.bf_export_words.restype = _i32
 _lib.bf_import_words.argtypes = [_vp, _vp, _u64, _vp]
 _lib.bf_import_words.restype = _i32
+class bf_batch_info_t(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_uint32),
+        ("nfilters", ctypes.c_uint32),
+        ("nkeys", ctypes.c_uint64),
+        ("ntiles", ctypes.c_uint64),
+        ("grid", ctypes.c_uint32),
+        ("tiles_per_class", ctypes.c_uint32 * 3),
+        ("mapping", bf_mapping_t * 3),
+    ]
+
+
+_lib.bf_batch_plan.argtypes = [ctypes.c_int, ctypes.POINTER(_vp), _u32, _vp,
+                               ctypes.POINTER(_u64), _vp, ctypes.POINTER(_vp)]
+_lib.bf_batch_plan.restype = _i32
+for _name in ("bf_batch_launch", "bf_batch_launch_direct", "bf_batch_launch_per_filter"):
+    getattr(_lib, _name).argtypes = [_vp, _vp]
+    getattr(_lib, _name).restype = _i32
+_lib.bf_batch_info.argtypes = [_vp, ctypes.POINTER(bf_batch_info_t)]
+_lib.bf_batch_info.restype = _i32
+_lib.bf_batch_destroy.argtypes = [_vp]
+_lib.bf_batch_destroy.restype = _i32
 _lib.bf_strerror.argtypes = [_i32]
 _lib.bf_strerror.restype = ctypes.c_char_p
 
@@ -145,6 +167,37 @@ def bf_export_words(f, dst: int, nbytes: int, stream: int = 0) -> int:
 
 def bf_import_words(f, src: int, nbytes: int, stream: int = 0) -> int:
     return _lib.bf_import_words(f, src, nbytes, stream)
+
+
+def bf_batch_plan(op: int, filters, d_keys: int, offsets, d_out: int = 0):
+    """Returns (status, plan).  filters: handles; offsets: nfilters + 1 ints."""
+    arr = (_vp * len(filters))(*[f.value if isinstance(f, _vp) else f for f in filters])
+    offs = (_u64 * len(offsets))(*[int(o) for o in offsets])
+    plan = _vp()
+    st = _lib.bf_batch_plan(op, arr, len(filters), d_keys, offs, d_out, ctypes.byref(plan))
+    return st, plan
+
+
+def bf_batch_launch(plan, stream: int = 0) -> int:
+    return _lib.bf_batch_launch(plan, stream)
+
+
+def bf_batch_launch_direct(plan, stream: int = 0) -> int:
+    return _lib.bf_batch_launch_direct(plan, stream)
+
+
+def bf_batch_launch_per_filter(plan, stream: int = 0) -> int:
+    return _lib.bf_batch_launch_per_filter(plan, stream)
+
+
+def bf_batch_info(plan):
+    info = bf_batch_info_t()
+    st = _lib.bf_batch_info(plan, ctypes.byref(info))
+    return st, info
+
+
+def bf_batch_destroy(plan) -> int:
+    return _lib.bf_batch_destroy(plan)
 
 
 def bf_strerror(status: int) -> str:
@@ -244,3 +297,45 @@ class BloomFilter:
 
     def size_bytes(self) -> int:
         return self.num_blocks * self.words_per_block * self.word_bits // 8
+
+
+class BatchPlan:
+    """One batched add or contains over many filters (include/bf_batch.h).
+
+    keys: one contiguous uint64/int64 CUDA tensor holding every filter's keys
+    back to back; offsets: nfilters + 1 host integers; out (contains): a uint8
+    CUDA tensor of the same length as keys.  The tensors must outlive the plan.
+    """
+
+    def __init__(self, op: int, filters, keys, offsets, out=None):
+        self._keep = (list(filters), keys, out)
+        st, plan = bf_batch_plan(op, [f.handle for f in filters], keys.data_ptr(), offsets,
+                                 out.data_ptr() if out is not None else 0)
+        _check(st, "bf_batch_plan")
+        self._plan = plan
+
+    def launch(self, stream=None) -> None:
+        _check(bf_batch_launch(self._plan, _stream_ptr(stream)), "bf_batch_launch")
+
+    def launch_direct(self, stream=None) -> None:
+        _check(bf_batch_launch_direct(self._plan, _stream_ptr(stream)), "bf_batch_launch_direct")
+
+    def launch_per_filter(self, stream=None) -> None:
+        _check(bf_batch_launch_per_filter(self._plan, _stream_ptr(stream)),
+               "bf_batch_launch_per_filter")
+
+    def info(self) -> bf_batch_info_t:
+        st, info = bf_batch_info(self._plan)
+        _check(st, "bf_batch_info")
+        return info
+
+    def close(self) -> None:
+        if self._plan:
+            _check(bf_batch_destroy(self._plan), "bf_batch_destroy")
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -9,6 +9,8 @@
 #include "bf_hash.hpp"
 #include "bf_kernels.hpp"
 #include "bf_registry.hpp"
+#include "bf_tuned.hpp"
+#include "bf_internal.hpp"
 
 namespace bfhip {
 
@@ -18,10 +20,10 @@ Registry& registry() {
 }
 
 namespace {
-
 std::once_flag g_registry_once;
+}  // namespace
 
-void init_registry() {
+void ensure_registry() {
   std::call_once(g_registry_once, [] {
     Registry& r = registry();
     register_u32_s1(r);
@@ -36,6 +38,8 @@ void init_registry() {
     register_u64_s16(r);
   });
 }
+
+namespace {
 
 // Zero fill with 16-byte stores (a kernel rather than hipMemsetAsync so a
 // captured graph holds no memset node).
@@ -59,38 +63,18 @@ bool is_pow2(uint32_t v) { return v != 0 && (v & (v - 1)) == 0; }
 
 using namespace bfhip;
 
-struct bf_filter {
-  uint64_t num_blocks;
-  uint32_t s;
-  uint32_t word_bits;
-  uint32_t k;
-  int32_t device;
-  uint64_t seed;
-  uint64_t nbytes;
-  void* d_words;
-  bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
-};
 
 namespace {
 
 bf_mapping_t default_mapping(const bf_filter* f, int op) {
+  const MapSpec t = tuned_map(op, static_cast<int>(f->word_bits), static_cast<int>(f->s),
+                              size_class_of(f->nbytes));
   bf_mapping_t m{};
-  const uint32_t block_bits = f->s * f->word_bits;
-  if (op == BF_OP_CONTAINS) {
-    // One lane per 256-bit slice of the block, whole slice per lane.
-    m.lanes_per_key = block_bits > 256 ? block_bits / 256 : 1;
-    m.words_per_lane = f->s / m.lanes_per_key;
-    m.keys_per_lane = 2;
-    m.atomic_bits = 0;
-  } else {
-    // One 64-bit atomic per lane, the group covering the block.
-    m.lanes_per_key = block_bits >= 64 ? block_bits / 64 : 1;
-    if (m.lanes_per_key > 16) m.lanes_per_key = 16;
-    m.words_per_lane = f->s / m.lanes_per_key;
-    m.keys_per_lane = 1;
-    m.atomic_bits = (f->word_bits == 32 && m.words_per_lane >= 2) ? 64 : 32;
-  }
-  m.max_workgroups = 0;
+  m.lanes_per_key = t.theta;
+  m.words_per_lane = t.phi;
+  m.keys_per_lane = t.kt;
+  m.atomic_bits = op == BF_OP_ADD ? t.atomic_bits : 0;
+  m.max_workgroups = t.max_workgroups;
   return m;
 }
 
@@ -135,7 +119,7 @@ bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
 
 bf_status launch(const bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                  void* stream) {
-  init_registry();
+  ensure_registry();
   bf_mapping_t m = resolve_mapping(f, op);
   // Keys per lane needs 8*KT-byte aligned keys (and KT-byte aligned results);
   // fall back to fewer keys per lane otherwise.

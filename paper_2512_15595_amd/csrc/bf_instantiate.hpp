@@ -3,6 +3,7 @@
 
 #include <utility>
 
+#include "bf_batch_kernels.hpp"
 #include "bf_kernels.hpp"
 #include "bf_registry.hpp"
 
@@ -53,8 +54,25 @@ void register_theta(Registry& r) {
   }
 }
 
+template <typename W, int S_WORDS, int K>
+void register_batch(Registry& r) {
+  constexpr int kBits = 8 * static_cast<int>(sizeof(W));
+  if constexpr (K == 0 || K >= S_WORDS) {
+    r.batch_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpAdd>);
+    r.batch_fn[batch_index(kOpContains, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpContains>);
+  }
+}
+
 template <typename W, int S_WORDS>
 void register_layout(Registry& r) {
+  register_batch<W, S_WORDS, 0>(r);
+  register_batch<W, S_WORDS, 4>(r);
+  register_batch<W, S_WORDS, 6>(r);
+  register_batch<W, S_WORDS, 8>(r);
+  register_batch<W, S_WORDS, 12>(r);
+  register_batch<W, S_WORDS, 16>(r);
   register_theta<W, S_WORDS, 0>(r);
   register_theta<W, S_WORDS, 4>(r);
   register_theta<W, S_WORDS, 6>(r);

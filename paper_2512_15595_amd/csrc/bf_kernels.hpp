@@ -221,114 +221,143 @@ __device__ __forceinline__ bool test_block(const W* words, uint32_t blk, uint32_
 }
 
 // ---------------------------------------------------------------------------
-// Kernels
+// One tile: up to 256 * KT consecutive keys handled by one 256-thread
+// workgroup, thread i taking keys [i*KT, i*KT + KT).  `count` is the number
+// of valid keys in the tile; `vec_ok` says the tile may use the packed
+// 8*KT-byte key loads and KT-byte result stores (full and aligned).
 // ---------------------------------------------------------------------------
-template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
-__global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp(lane & (THETA - 1));
-  W* words = static_cast<W*>(a.words);
-  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
-  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
+struct FilterView {
+  void* words;
+  uint64_t hash_init;
+  uint32_t nb_lo;
+  uint32_t nb_hi_mask;
+};
 
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint64_t first = tile * kTile + static_cast<uint64_t>(threadIdx.x) * KT;
-    const bool full = (tile + 1) * kTile <= a.n;
-    uint64_t key[KT];
-    if (full) {
-      load_keys<KT>(a.keys + first, key);
-    } else {
+template <int KT>
+__device__ __forceinline__ void hash_tile_keys(const FilterView& fv, const uint64_t* keys,
+                                               uint32_t count, bool vec_ok, uint32_t (&blk)[KT],
+                                               uint32_t (&lo)[KT]) {
+  const uint32_t first = threadIdx.x * KT;
+  uint64_t key[KT];
+  if (vec_ok) {
+    load_keys<KT>(keys + first, key);
+  } else {
 #pragma unroll
-      for (int t = 0; t < KT; ++t) key[t] = (first + t < a.n) ? a.keys[first + t] : 0;
-    }
-    uint32_t blk[KT], lo[KT];
+    for (int t = 0; t < KT; ++t) key[t] = (first + t < count) ? keys[first + t] : 0;
+  }
+#pragma unroll
+  for (int t = 0; t < KT; ++t) {
+    const uint64_t h = xxh64_u64(key[t], fv.hash_init);
+    blk[t] = block_of(h, fv.nb_lo, fv.nb_hi_mask);
+    lo[t] = static_cast<uint32_t>(h);
+  }
+}
+
+template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
+__device__ __forceinline__ void add_tile(const FilterView& fv, const uint64_t* keys, uint32_t count,
+                                         bool vec_ok, uint32_t k,
+                                         const LanePatterns<W, S_WORDS, K, THETA, PHI>& lp) {
+  const uint32_t lane = threadIdx.x & 63u;
+  W* words = static_cast<W*>(fv.words);
+  uint32_t blk[KT], lo[KT];
+  hash_tile_keys<KT>(fv, keys, count, vec_ok, blk, lo);
+  if constexpr (THETA == 1) {
+    const uint32_t first = threadIdx.x * KT;
+#pragma unroll
+    for (int t = 0; t < KT; ++t)
+      if (vec_ok || first + t < count)
+        add_block<W, S_WORDS, K, 1, PHI, ATOM64>(words, blk[t], lo[t], lp, k);
+  } else {
+    const uint32_t group_first = (threadIdx.x & ~static_cast<uint32_t>(THETA - 1)) * KT;
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-      const uint64_t h = xxh64_u64(key[t], a.hash_init);
-      blk[t] = block_of(h, a.nb_lo, a.nb_hi_mask);
-      lo[t] = static_cast<uint32_t>(h);
-    }
-    if constexpr (THETA == 1) {
-#pragma unroll
-      for (int t = 0; t < KT; ++t)
-        if (full || first + t < a.n) add_block<W, S_WORDS, K, 1, PHI, ATOM64>(words, blk[t], lo[t], lp, a.k);
-    } else {
-      const uint64_t group_first =
-          tile * kTile + static_cast<uint64_t>(threadIdx.x & ~static_cast<uint32_t>(THETA - 1)) * KT;
-#pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        [&]<int... R>(std::integer_sequence<int, R...>) {
-          ([&] {
-            const uint32_t b = group_bcast<THETA, R>(blk[t], lane);
-            const uint32_t l = group_bcast<THETA, R>(lo[t], lane);
-            if (full || group_first + static_cast<uint64_t>(R) * KT + t < a.n)
-              add_block<W, S_WORDS, K, THETA, PHI, ATOM64>(words, b, l, lp, a.k);
-          }(), ...);
-        }(std::make_integer_sequence<int, THETA>{});
-      }
+      [&]<int... R>(std::integer_sequence<int, R...>) {
+        ([&] {
+          const uint32_t b = group_bcast<THETA, R>(blk[t], lane);
+          const uint32_t l = group_bcast<THETA, R>(lo[t], lane);
+          if (vec_ok || group_first + static_cast<uint32_t>(R) * KT + t < count)
+            add_block<W, S_WORDS, K, THETA, PHI, ATOM64>(words, b, l, lp, k);
+        }(), ...);
+      }(std::make_integer_sequence<int, THETA>{});
     }
   }
 }
 
 template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT>
-__global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
+__device__ __forceinline__ void contains_tile(const FilterView& fv, const uint64_t* keys,
+                                              uint8_t* out, uint32_t count, bool vec_ok,
+                                              uint32_t k,
+                                              const LanePatterns<W, S_WORDS, K, THETA, PHI>& lp) {
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t rank = lane & (THETA - 1);
-  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp(rank);
-  const W* words = static_cast<const W*>(a.words);
-  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
-  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
-
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint64_t first = tile * kTile + static_cast<uint64_t>(threadIdx.x) * KT;
-    const bool full = (tile + 1) * kTile <= a.n;
-    uint64_t key[KT];
-    if (full) {
-      load_keys<KT>(a.keys + first, key);
-    } else {
-#pragma unroll
-      for (int t = 0; t < KT; ++t) key[t] = (first + t < a.n) ? a.keys[first + t] : 0;
-    }
-    uint32_t blk[KT], lo[KT];
+  const W* words = static_cast<const W*>(fv.words);
+  uint32_t blk[KT], lo[KT];
+  hash_tile_keys<KT>(fv, keys, count, vec_ok, blk, lo);
+  uint32_t res[KT];
+  if constexpr (THETA == 1) {
 #pragma unroll
     for (int t = 0; t < KT; ++t) {
-      const uint64_t h = xxh64_u64(key[t], a.hash_init);
-      blk[t] = block_of(h, a.nb_lo, a.nb_hi_mask);
-      lo[t] = static_cast<uint32_t>(h);
+      // Out-of-range keys of a partial tile are hashed as key 0 and read an
+      // in-range block; their result is never stored.
+      res[t] = test_block<W, S_WORDS, K, 1, PHI>(words, blk[t], lo[t], lp, k) ? 1u : 0u;
     }
-    uint32_t res[KT];
-    if constexpr (THETA == 1) {
+  } else {
+    const uint32_t group_shift = lane & ~static_cast<uint32_t>(THETA - 1);
+    constexpr uint64_t kGroupMask = (1ull << THETA) - 1ull;
 #pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        // Out-of-range keys of the tail tile are hashed (garbage) but read
-        // an in-range block, and their result is never stored.
-        res[t] = test_block<W, S_WORDS, K, 1, PHI>(words, blk[t], lo[t], lp, a.k) ? 1u : 0u;
-      }
-    } else {
-      const uint32_t group_shift = lane & ~static_cast<uint32_t>(THETA - 1);
-      constexpr uint64_t kGroupMask = (THETA == 64) ? ~0ull : ((1ull << THETA) - 1ull);
-#pragma unroll
-      for (int t = 0; t < KT; ++t) {
-        res[t] = 0;
-        [&]<int... R>(std::integer_sequence<int, R...>) {
-          ([&] {
-            const uint32_t b = group_bcast<THETA, R>(blk[t], lane);
-            const uint32_t l = group_bcast<THETA, R>(lo[t], lane);
-            const bool ok = test_block<W, S_WORDS, K, THETA, PHI>(words, b, l, lp, a.k);
-            const uint64_t fails = __ballot(!ok);
-            const bool group_ok = ((fails >> group_shift) & kGroupMask) == 0;
-            if (rank == static_cast<uint32_t>(R)) res[t] = group_ok ? 1u : 0u;
-          }(), ...);
-        }(std::make_integer_sequence<int, THETA>{});
-      }
+    for (int t = 0; t < KT; ++t) {
+      res[t] = 0;
+      [&]<int... R>(std::integer_sequence<int, R...>) {
+        ([&] {
+          const uint32_t b = group_bcast<THETA, R>(blk[t], lane);
+          const uint32_t l = group_bcast<THETA, R>(lo[t], lane);
+          const bool ok = test_block<W, S_WORDS, K, THETA, PHI>(words, b, l, lp, k);
+          const uint64_t fails = __ballot(!ok);
+          const bool group_ok = ((fails >> group_shift) & kGroupMask) == 0;
+          if (rank == static_cast<uint32_t>(R)) res[t] = group_ok ? 1u : 0u;
+        }(), ...);
+      }(std::make_integer_sequence<int, THETA>{});
     }
-    if (full) {
-      store_results<KT>(a.out + first, res);
-    } else {
+  }
+  const uint32_t first = threadIdx.x * KT;
+  if (vec_ok) {
+    store_results<KT>(out + first, res);
+  } else {
 #pragma unroll
-      for (int t = 0; t < KT; ++t)
-        if (first + t < a.n) a.out[first + t] = static_cast<uint8_t>(res[t]);
-    }
+    for (int t = 0; t < KT; ++t)
+      if (first + t < count) out[first + t] = static_cast<uint8_t>(res[t]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Single-filter kernels: a grid-stride walk over the tiles of one key array.
+// The host guarantees 8*KT-byte aligned keys and KT-byte aligned results.
+// ---------------------------------------------------------------------------
+template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
+__global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
+  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+  const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
+  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
+  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t base = tile * kTile;
+    const uint32_t count = static_cast<uint32_t>(a.n - base < kTile ? a.n - base : kTile);
+    add_tile<W, S_WORDS, K, THETA, PHI, KT, ATOM64>(fv, a.keys + base, count, count == kTile,
+                                                    a.k, lp);
+  }
+}
+
+template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT>
+__global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
+  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+  const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
+  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
+  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
+  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const uint64_t base = tile * kTile;
+    const uint32_t count = static_cast<uint32_t>(a.n - base < kTile ? a.n - base : kTile);
+    contains_tile<W, S_WORDS, K, THETA, PHI, KT>(fv, a.keys + base, a.out + base, count,
+                                                 count == kTile, a.k, lp);
   }
 }
 

@@ -47,11 +47,21 @@ inline int registry_index(int op, int word_bits, int s, int kidx, int theta, int
 
 constexpr int kRegistrySize = 2 * 2 * kLog2Max * kNumK * kLog2Max * kLog2Max * kKtLog2Max * 2;
 
+inline int batch_index(int op, int word_bits, int s, int kidx) {
+  return ((op * 2 + (word_bits == 64 ? 1 : 0)) * kLog2Max + ilog2(s)) * kNumK + kidx;
+}
+
+constexpr int kBatchRegistrySize = 2 * 2 * kLog2Max * kNumK;
+
 struct Registry {
   const void* fn[kRegistrySize];
+  const void* batch_fn[kBatchRegistrySize];  // persistent batched kernels
 };
 
 Registry& registry();
+
+// Fills the registry on first use (thread-safe).
+void ensure_registry();
 
 // Registration hooks, one per (word width, words per block).
 void register_u32_s1(Registry&);

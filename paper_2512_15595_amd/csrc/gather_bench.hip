@@ -83,6 +83,49 @@ __global__ __launch_bounds__(kThreads) void random_read_kernel(const uint8_t* bu
   if (acc == 0x9e3779b9u) sink[0] = acc;  // practically never; keeps the loads
 }
 
+// 16-byte load with an explicit cache policy: 1 = nontemporal hint,
+// 2 = sc1 (system coherence scope), 3 = sc0 sc1, 4 = nt sc1.
+template <int POL>
+__device__ __forceinline__ u32x4 load16_policy(const uint8_t* p) {
+  if constexpr (POL == 1) {
+    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+  } else {
+    u32x4 v;
+    if constexpr (POL == 2)
+      asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
+    else if constexpr (POL == 3)
+      asm volatile("global_load_dwordx4 %0, %1, off sc0 sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
+    else
+      asm volatile("global_load_dwordx4 %0, %1, off nt sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
+    return v;
+  }
+}
+
+// Random SEG-byte reads (one lane per segment) with cache policy POL.
+template <int SEG, int POL>
+__global__ __launch_bounds__(kThreads) void random_read_policy_kernel(const uint8_t* buf,
+                                                                      uint64_t n_access,
+                                                                      uint32_t nseg_lo,
+                                                                      uint32_t nseg_hi_mask,
+                                                                      uint32_t seed, uint32_t* sink) {
+  const uint64_t tid = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x;
+  const uint64_t threads = static_cast<uint64_t>(gridDim.x) * kThreads;
+  uint32_t acc = 0;
+#pragma unroll
+  for (int r = 0; r < kAccessPerThread; ++r) {
+    const uint64_t a = tid + static_cast<uint64_t>(r) * threads;
+    if (a < n_access) {
+      const uint64_t seg = segment_of(a, seed, nseg_lo, nseg_hi_mask);
+#pragma unroll
+      for (int i = 0; i < SEG / 16; ++i) {
+        u32x4 v = load16_policy<POL>(buf + seg * SEG + 16 * i);
+        acc ^= v.x ^ v.y ^ v.z ^ v.w;
+      }
+    }
+  }
+  if (acc == 0x9e3779b9u) sink[0] = acc;
+}
+
 template <int SEG>
 __global__ __launch_bounds__(kThreads) void random_read_indexed_kernel(const uint8_t* buf,
                                                                        uint64_t nseg,
@@ -216,6 +259,34 @@ int bfb_random_read(const void* d_buf, uint64_t buf_bytes, uint32_t seg_bytes,
     case (128ull << 8) | 8: return launch_read<128, 8>(d_buf, nseg, n_access, seed, d_sink, s);
     default: return BFB_EINVAL;
   }
+}
+
+int bfb_random_read_policy(const void* d_buf, uint64_t buf_bytes, uint32_t seg_bytes,
+                           uint32_t policy, uint64_t n_access, uint32_t seed, uint32_t* d_sink,
+                           void* stream) {
+  if (d_buf == nullptr || d_sink == nullptr || (seg_bytes != 32 && seg_bytes != 128)) return BFB_EINVAL;
+  if (policy < 1 || policy > 4) return BFB_EINVAL;
+  if (n_access == 0) return BFB_OK;
+  uint32_t lo, him;
+  if (!split_count(buf_bytes / seg_bytes, &lo, &him)) return BFB_EINVAL;
+  const uint64_t threads = (n_access + kAccessPerThread - 1) / kAccessPerThread;
+  if (threads > (1ull << 22) * kThreads) return BFB_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const dim3 grid(grid_for(threads)), block(kThreads);
+  const uint8_t* b = static_cast<const uint8_t*>(d_buf);
+  const uint32_t key = seg_bytes * 10 + policy;
+  switch (key) {
+    case 321: hipLaunchKernelGGL((random_read_policy_kernel<32, 1>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 322: hipLaunchKernelGGL((random_read_policy_kernel<32, 2>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 323: hipLaunchKernelGGL((random_read_policy_kernel<32, 3>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 324: hipLaunchKernelGGL((random_read_policy_kernel<32, 4>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 1281: hipLaunchKernelGGL((random_read_policy_kernel<128, 1>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 1282: hipLaunchKernelGGL((random_read_policy_kernel<128, 2>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 1283: hipLaunchKernelGGL((random_read_policy_kernel<128, 3>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    case 1284: hipLaunchKernelGGL((random_read_policy_kernel<128, 4>), grid, block, 0, s, b, n_access, lo, him, seed, d_sink); break;
+    default: return BFB_EINVAL;
+  }
+  return hipGetLastError() == hipSuccess ? BFB_OK : BFB_EDEVICE;
 }
 
 int bfb_fill_random_index(uint64_t* d_idx, uint64_t n, uint64_t nseg, uint32_t seed, void* stream) {

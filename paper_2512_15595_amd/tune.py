@@ -113,12 +113,25 @@ def sweep_layout(torch, s: int, word_bits: int, k: int, filter_bytes: int, n_key
     return records
 
 
-def best_per_class(records):
-    best = {}
+def _simplicity(r):
+    # fewer cooperating lanes, wider per-lane chunks, two keys per lane first
+    return (r["lanes_per_key"], -r["words_per_lane"], abs(r["keys_per_lane"] - 2),
+            -r["atomic_bits"], r["max_workgroups"])
+
+
+def best_per_class(records, tolerance: float = 0.01):
+    """Fastest mapping per (op, word bits, words per block, size class);
+    mappings within `tolerance` of the fastest count as ties and the simplest
+    of them is taken, so run-to-run noise does not pick exotic layouts."""
+    groups = {}
     for r in records:
         key = (r["op"], r["word_bits"], r["words_per_block"], r["size_class"])
-        if key not in best or r["gkeys_s"] > best[key]["gkeys_s"]:
-            best[key] = r
+        groups.setdefault(key, []).append(r)
+    best = {}
+    for key, rs in groups.items():
+        top = max(r["gkeys_s"] for r in rs)
+        ties = [r for r in rs if r["gkeys_s"] >= (1.0 - tolerance) * top]
+        best[key] = min(ties, key=_simplicity)
     return best
 
 

@@ -103,3 +103,65 @@ def kmer_keys(n_bases: int, seed: int, k: int = 31, segment: int = 1000,
     for i in range(k):
         out = (out << np.uint64(2)) | seq[i:i + nk].astype(np.uint64)
     return out
+
+
+def zipf_counts(nitems: int, total: int, exponent: float = 1.1, lo: int = 100,
+                hi: int = 10_000_000, seed: int = 4) -> np.ndarray:
+    """Per-item counts c_r = clip(a * r^-exponent, lo, hi) for ranks r = 1..n,
+    with a chosen so the counts sum to `total` (bisection on a, then
+    largest-remainder rounding); ranks are given to items by a seeded
+    permutation."""
+    r = np.arange(1, nitems + 1, dtype=np.float64) ** (-exponent)
+
+    def total_for(a):
+        return np.clip(a * r, lo, hi).sum()
+
+    a_lo, a_hi = 0.0, float(hi) * 2
+    while total_for(a_hi) < total and a_hi < 1e30:
+        a_hi *= 2
+    for _ in range(200):
+        mid = 0.5 * (a_lo + a_hi)
+        if total_for(mid) < total:
+            a_lo = mid
+        else:
+            a_hi = mid
+    c = np.clip(a_hi * r, lo, hi)
+    c = c * (total / c.sum())
+    base = np.floor(c).astype(np.int64)
+    short = int(total - base.sum())
+    if short > 0:
+        base[np.argsort(-(c - base))[:short]] += 1
+    return base[rng(seed).permutation(nitems)]
+
+
+def log_uniform_sizes(nitems: int, lo_bytes: int, hi_bytes: int, align: int, seed: int) -> np.ndarray:
+    """Sizes log-uniform on [lo, hi], rounded to a multiple of `align`."""
+    u = rng(seed).random(nitems)
+    sizes = np.exp(np.log(lo_bytes) + u * (np.log(hi_bytes) - np.log(lo_bytes)))
+    return np.maximum(align, np.round(sizes / align).astype(np.int64) * align)
+
+
+def batched_workload(nfilters: int = 4096, total_keys: int = 2**28, lo_bytes: int = 4 << 10,
+                     hi_bytes: int = 16 << 20, block_bytes: int = 32, seed: int = 4,
+                     max_count: int = 10_000_000, min_count: int = 100):
+    """Many independent filters: sizes log-uniform on [4 KiB, 16 MiB] (rounded
+    to whole blocks), key counts Zipf(1.1) clipped to [1e2, 1e7] summing to
+    total_keys.  Returns (sizes_bytes, offsets, keys, queries) where filter i
+    owns keys[offsets[i]:offsets[i+1]] and the same range of queries; half
+    of each filter's queries are its own inserted keys, half fresh keys."""
+    sizes = log_uniform_sizes(nfilters, lo_bytes, hi_bytes, block_bytes, seed)
+    counts = zipf_counts(nfilters, total_keys, 1.1, min_count, max_count, seed + 1)
+    offsets = np.zeros(nfilters + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    keys = uniform_keys(int(offsets[-1]), seed + 2)
+    fresh = uniform_keys(int(offsets[-1]), seed + 3)
+    g = rng(seed + 4)
+    # per position: hit (a key of the same filter, chosen by an in-filter
+    # offset) or miss, each with probability 1/2
+    owner = np.repeat(np.arange(nfilters), counts)
+    start = offsets[:-1][owner]
+    pick = start + (g.random(owner.size) * counts[owner]).astype(np.int64)
+    hits = keys[pick]
+    take = g.random(owner.size) < 0.5
+    queries = np.where(take, hits, fresh)
+    return sizes, offsets, keys, queries
