@@ -281,9 +281,146 @@ def run_batched(args) -> dict:
     return res
 
 
+def water_fill_sizes(n: int, total: int, lo: int, hi: int, align: int, seed: int):
+    """Log-uniform sizes on [lo, hi], scaled to sum to `total` with every
+    size clipped to hi (scale, clip, repeat), rounded down to `align`."""
+    import numpy as np
+
+    from paper_2512_15595_amd import workloads
+
+    sizes = workloads.log_uniform_sizes(n, lo, hi, align, seed).astype(np.float64)
+    for _ in range(100):
+        free = sizes < hi
+        rest = total - sizes[~free].sum()
+        sizes[free] *= rest / sizes[free].sum()
+        sizes = np.minimum(sizes, hi)
+        if abs(sizes.sum() - total) < align * n:
+            break
+    return (np.floor(sizes / align) * align).astype(np.int64)
+
+
+def latency_summary(res, ns) -> dict:
+    import numpy as np
+
+    arr = np.array([r.arrival_ns for r in res], dtype=np.float64)
+    done = np.array([r.complete_ns for r in res], dtype=np.float64)
+    lat = (done - arr) / 1e6
+    span = (done.max() - arr.min()) / 1e9
+    return {"throughput_gkeys_s": round(float(np.sum(ns)) / span / 1e9, 3),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "mean_ms": round(float(lat.mean()), 3), "makespan_s": round(span, 4)}
+
+
+def run_serve(args) -> dict:
+    """64 device-resident filters (32 GiB), a Poisson stream of contains and
+    add requests (9:1, sizes log-uniform 1e3..1.6e7 keys, 50 % hits), served
+    with continuous batching under a 48 GiB working budget, against serial
+    execution of the same schedule."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2512_15595_amd import bf as bfmod
+    from paper_2512_15595_amd import workloads
+    from paper_2512_15595_amd.bf import BloomFilter, Server
+
+    lib = ctypes.CDLL(bfmod.LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    lib.bfb_fill_splitmix64.argtypes = [vp, u64, u64, u64, vp]
+    lib.bfb_fill_mixed_queries.argtypes = [vp, u64, u64, u64, u32, u64, u64, u32, u64, vp]
+    stream = torch.cuda.current_stream().cuda_stream
+    s, S, k = args.words_per_block, args.word_bits, args.k
+    block = s * S // 8
+    nf = args.serve_filters
+    total_bytes = args.serve_total_gib << 30
+    sizes = water_fill_sizes(nf, total_bytes, 64 << 20, 1 << 30, block, 5)
+    log(f"[bench] serve: {nf} filters, {sizes.sum() / 2**30:.2f} GiB; pre-populating at 32 bits/key")
+    filters = [BloomFilter(int(sz) // block, s, S, k, 100 + i) for i, sz in enumerate(sizes)]
+    chunk = 1 << 27
+    buf = torch.empty(chunk, dtype=torch.int64, device="cuda")
+    prepop = [int(sz) // 4 for sz in sizes]
+    for i, f in enumerate(filters):
+        for first in range(0, prepop[i], chunk):
+            m = min(chunk, prepop[i] - first)
+            assert lib.bfb_fill_splitmix64(buf.data_ptr(), m, 900 + i, first, stream) == 0
+            f.add(buf[:m])
+    del buf
+    max_n = 16_000_000
+    pool_n = max_n + 1024
+    pools = torch.empty((nf, pool_n), dtype=torch.int64, device="cuda")
+    outs = torch.empty((nf, pool_n), dtype=torch.uint8, device="cuda")
+    for i in range(nf):
+        assert lib.bfb_fill_mixed_queries(pools[i].data_ptr(), pool_n, 900 + i, 0, min(prepop[i], 2**32 - 1),
+                                          3000 + i, 0, 1 << 31, 4000 + i, stream) == 0
+    torch.cuda.synchronize()
+    log("[bench] serve: filters and request pools resident")
+
+    g = workloads.rng(11)
+    nreq = args.serve_requests
+    ops = np.where(g.random(nreq) < 0.1, 0, 1)
+    filt = g.integers(0, nf, size=nreq)
+    ns = np.exp(np.log(1e3) + g.random(nreq) * (np.log(1.6e7) - np.log(1e3))).astype(np.int64)
+    offs = (g.integers(0, pool_n - ns) // 2) * 2
+    kp = [pools[filt[i]].data_ptr() + 8 * int(offs[i]) for i in range(nreq)]
+    op_ = [outs[filt[i]].data_ptr() + int(offs[i]) if ops[i] == 1 else 0 for i in range(nreq)]
+    budget = (48 << 30) - int(sizes.sum())
+    srv = Server(filters, hbm_budget_bytes=budget, max_inflight=args.serve_inflight,
+                 nstreams=args.serve_streams, coalesce_max_keys=args.serve_coalesce_keys)
+
+    # serial capacity: every request present at time 0, one after another
+    ncap = min(nreq, 2000)
+    reqs0 = srv.requests(ops[:ncap], filt[:ncap], kp[:ncap], ns[:ncap], op_[:ncap], np.zeros(ncap))
+    cap_res = srv.replay(reqs0, serial=True)
+    cap = latency_summary(cap_res, ns[:ncap])["throughput_gkeys_s"] * 1e9
+    log(f"[bench] serve: serial capacity {cap / 1e9:.2f} Gkeys/s")
+    runs = {}
+    mean_n = float(ns.mean())
+    for load in args.serve_loads:
+        rate = load * cap / mean_n  # requests per second
+        arr = np.cumsum(workloads.rng(20 + int(load * 10)).exponential(1.0 / rate, size=nreq)) * 1e9
+        reqs = srv.requests(ops, filt, kp, ns, op_, arr.astype(np.int64))
+        served = latency_summary(srv.replay(reqs), ns)
+        serial = latency_summary(srv.replay(reqs, serial=True), ns)
+        runs[str(load)] = {"served": served, "serial": serial,
+                           "throughput_ratio": round(served["throughput_gkeys_s"] / serial["throughput_gkeys_s"], 3),
+                           "p99_ratio_serial_over_served": round(serial["p99_ms"] / max(served["p99_ms"], 1e-9), 3)}
+        log(f"[bench] serve load {load}: {runs[str(load)]}")
+    st = srv.stats().as_dict()
+    srv.close()
+    hi_load = runs[str(max(args.serve_loads))]
+    res = {
+        "metric": "served Gkeys/s and p50/p99 latency, 64 filters x 32 GiB, Poisson contains:add 9:1",
+        "value": hi_load["served"]["throughput_gkeys_s"],
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"serve_{nf}_filters_{sizes.sum() >> 30}GiB_sbf_{s}x{S}_k{k}",
+                   "requests": nreq, "mean_keys_per_request": round(mean_n), "hbm_budget_bytes": budget,
+                   "max_inflight": args.serve_inflight, "streams": args.serve_streams,
+                   "coalesce_max_keys": args.serve_coalesce_keys},
+        "serial_capacity_gkeys_s": round(cap / 1e9, 3),
+        "loads": runs,
+        "server_stats": st,
+    }
+    for f in filters:
+        f.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["dram", "batched"], default="dram")
+    ap.add_argument("--serve-filters", type=int, default=64)
+    ap.add_argument("--serve-total-gib", type=int, default=32)
+    ap.add_argument("--serve-requests", type=int, default=6000)
+    ap.add_argument("--serve-loads", type=float, nargs="+", default=[0.5, 0.9, 2.0])
+    ap.add_argument("--serve-inflight", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-coalesce-keys", type=int, default=65536)
+    ap.add_argument("--workload", choices=["dram", "batched", "serve"], default="dram")
     ap.add_argument("--batch-filters", type=int, default=4096)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -317,6 +454,9 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
         print(json.dumps(run_batched(args)), flush=True)
+        return 0
+    if args.workload == "serve":
+        print(json.dumps(run_serve(args)), flush=True)
         return 0
     n = 1 << args.log2_keys
     s, S, k = args.words_per_block, args.word_bits, args.k

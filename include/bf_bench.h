@@ -68,6 +68,20 @@ int bfb_random_atomic_or(void *d_buf, uint64_t buf_bytes, uint32_t seg_bytes,
  * (non-atomic, as in the HPC Challenge RandomAccess kernel). */
 int bfb_gups(void *d_buf, uint64_t buf_bytes, uint64_t n_updates, uint32_t seed, void *stream);
 
+/* Seeded synthetic keys on the device (workload generation, not part of
+ * the filter method).  SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): element
+ * i of stream `seed` is the SplitMix64 output function of
+ * seed + (i + 1) * 0x9E3779B97F4A7C15.  Writes elements first..first+n-1. */
+int bfb_fill_splitmix64(uint64_t *d_out, uint64_t n, uint64_t seed, uint64_t first, void *stream);
+
+/* Lookup keys with a hit fraction: out[i] is, when the upper half of mix
+ * element i is below hit_q32, source element src_first + j with
+ * j = floor(lo32(mix element i) * src_count / 2^32), else fresh element
+ * fresh_first + i. */
+int bfb_fill_mixed_queries(uint64_t *d_out, uint64_t n, uint64_t src_seed, uint64_t src_first,
+                           uint32_t src_count, uint64_t fresh_seed, uint64_t fresh_first,
+                           uint32_t hit_q32, uint64_t mix_seed, void *stream);
+
 /* Streaming copy of `bytes` (a multiple of 16) from src to dst. */
 int bfb_copy(void *d_dst, const void *d_src, uint64_t bytes, void *stream);
 

@@ -103,6 +103,66 @@ _lib.bf_batch_info.argtypes = [_vp, ctypes.POINTER(bf_batch_info_t)]
 _lib.bf_batch_info.restype = _i32
 _lib.bf_batch_destroy.argtypes = [_vp]
 _lib.bf_batch_destroy.restype = _i32
+class bf_server_config_t(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("max_inflight", ctypes.c_uint32),
+        ("nstreams", ctypes.c_uint32),
+        ("coalesce_max_keys", ctypes.c_uint64),
+        ("coalesce_max_requests", ctypes.c_uint32),
+        ("coalesce_max_tiles", ctypes.c_uint32),
+    ]
+
+
+class bf_request_t(ctypes.Structure):
+    _fields_ = [
+        ("op", ctypes.c_uint32),
+        ("filter", ctypes.c_uint32),
+        ("d_keys", ctypes.c_void_p),
+        ("n", ctypes.c_uint64),
+        ("d_out", ctypes.c_void_p),
+        ("arrival_ns", ctypes.c_uint64),
+    ]
+
+
+class bf_request_result_t(ctypes.Structure):
+    _fields_ = [
+        ("arrival_ns", ctypes.c_uint64),
+        ("admit_ns", ctypes.c_uint64),
+        ("complete_ns", ctypes.c_uint64),
+        ("launch", ctypes.c_uint32),
+        ("status", ctypes.c_int32),
+    ]
+
+
+class bf_server_stats_t(ctypes.Structure):
+    _fields_ = [
+        ("requests", ctypes.c_uint64),
+        ("launches", ctypes.c_uint64),
+        ("coalesced_launches", ctypes.c_uint64),
+        ("peak_inflight_bytes", ctypes.c_uint64),
+        ("peak_inflight_launches", ctypes.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {name: int(getattr(self, name)) for name, _ in self._fields_}
+
+
+_lib.bf_server_create.argtypes = [ctypes.POINTER(_vp), _u32, ctypes.POINTER(bf_server_config_t),
+                                  ctypes.POINTER(_vp)]
+_lib.bf_server_create.restype = _i32
+_lib.bf_server_submit.argtypes = [_vp, ctypes.POINTER(bf_request_t), ctypes.POINTER(_u64)]
+_lib.bf_server_submit.restype = _i32
+_lib.bf_server_wait.argtypes = [_vp, ctypes.POINTER(_u64), _u64, ctypes.POINTER(bf_request_result_t)]
+_lib.bf_server_wait.restype = _i32
+for _name in ("bf_server_replay", "bf_server_replay_serial"):
+    getattr(_lib, _name).argtypes = [_vp, ctypes.POINTER(bf_request_t), _u64,
+                                     ctypes.POINTER(bf_request_result_t)]
+    getattr(_lib, _name).restype = _i32
+_lib.bf_server_stats.argtypes = [_vp, ctypes.POINTER(bf_server_stats_t)]
+_lib.bf_server_stats.restype = _i32
+_lib.bf_server_destroy.argtypes = [_vp]
+_lib.bf_server_destroy.restype = _i32
 _lib.bf_strerror.argtypes = [_i32]
 _lib.bf_strerror.restype = ctypes.c_char_p
 
@@ -333,6 +393,64 @@ class BatchPlan:
         if self._plan:
             _check(bf_batch_destroy(self._plan), "bf_batch_destroy")
             self._plan = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """The request loop of include/bf_serve.h over a list of BloomFilter."""
+
+    def __init__(self, filters, hbm_budget_bytes: int = 16 << 30, max_inflight: int = 16,
+                 nstreams: int = 8, coalesce_max_keys: int = 65536,
+                 coalesce_max_requests: int = 256, coalesce_max_tiles: int = 16384):
+        self._filters = list(filters)
+        cfg = bf_server_config_t(hbm_budget_bytes, max_inflight, nstreams, coalesce_max_keys,
+                                 coalesce_max_requests, coalesce_max_tiles)
+        arr = (_vp * len(self._filters))(*[f.handle.value for f in self._filters])
+        h = _vp()
+        _check(_lib.bf_server_create(arr, len(self._filters), ctypes.byref(cfg), ctypes.byref(h)),
+               "bf_server_create")
+        self._h = h
+
+    @staticmethod
+    def requests(ops, filters, keys_ptrs, ns, out_ptrs, arrivals_ns):
+        n = len(ops)
+        reqs = (bf_request_t * n)()
+        for i in range(n):
+            reqs[i] = bf_request_t(int(ops[i]), int(filters[i]), int(keys_ptrs[i]), int(ns[i]),
+                                   int(out_ptrs[i]) if out_ptrs[i] else None, int(arrivals_ns[i]))
+        return reqs
+
+    def replay(self, reqs, serial: bool = False):
+        res = (bf_request_result_t * len(reqs))()
+        fn = _lib.bf_server_replay_serial if serial else _lib.bf_server_replay
+        _check(fn(self._h, reqs, len(reqs), res), "bf_server_replay")
+        return res
+
+    def submit(self, req: bf_request_t) -> int:
+        rid = _u64()
+        _check(_lib.bf_server_submit(self._h, ctypes.byref(req), ctypes.byref(rid)), "bf_server_submit")
+        return int(rid.value)
+
+    def wait(self, ids):
+        arr = (_u64 * len(ids))(*ids)
+        res = (bf_request_result_t * len(ids))()
+        _check(_lib.bf_server_wait(self._h, arr, len(ids), res), "bf_server_wait")
+        return res
+
+    def stats(self) -> bf_server_stats_t:
+        st = bf_server_stats_t()
+        _check(_lib.bf_server_stats(self._h, ctypes.byref(st)), "bf_server_stats")
+        return st
+
+    def close(self) -> None:
+        if self._h:
+            _check(_lib.bf_server_destroy(self._h), "bf_server_destroy")
+            self._h = None
 
     def __del__(self):
         try:

@@ -163,6 +163,8 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
     descs[i].hash_init = xxh64_u64_init(f->seed);
     descs[i].nb_lo = static_cast<uint32_t>(f->num_blocks);
     descs[i].nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
+    descs[i].keys = d_keys;
+    descs[i].out = d_out;
     descs[i].reserved = 0;
   }
   const size_t tiles_bytes = std::max<size_t>(1, tiles.size()) * sizeof(BatchTile);
@@ -182,8 +184,6 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
 
   b->args.filters = b->d_filters;
   b->args.tiles = b->d_tiles;
-  b->args.keys = d_keys;
-  b->args.out = d_out;
   b->args.ntiles = b->ntiles;
   b->args.k = f0->k;
 

@@ -14,11 +14,13 @@
 
 namespace bfhip {
 
-struct BatchFilter {  // 32 bytes
+struct BatchFilter {  // 48 bytes: one filter (or one request on a filter)
   void* words;
   uint64_t hash_init;
   uint32_t nb_lo;
   uint32_t nb_hi_mask;
+  const uint64_t* keys;  // tile key_start indexes into keys / out
+  uint8_t* out;
   uint64_t reserved;
 };
 
@@ -35,8 +37,6 @@ constexpr uint32_t kTileVecBit = 1u << 18;
 struct BatchArgs {
   const BatchFilter* filters;
   const BatchTile* tiles;
-  const uint64_t* keys;
-  uint8_t* out;
   uint64_t ntiles;
   uint32_t k;
   uint32_t pad;
@@ -55,7 +55,7 @@ constexpr MapSpec batch_map() {
 
 template <typename W, int S_WORDS, int K, int OP, int CLS>
 __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchTile& t,
-                                           const FilterView& fv) {
+                                           const BatchFilter& f, const FilterView& fv) {
   constexpr MapSpec m = batch_map<W, S_WORDS, K, OP, CLS>();
   constexpr int kTheta = static_cast<int>(m.theta);
   constexpr int kPhi = static_cast<int>(m.phi);
@@ -66,10 +66,10 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchTile& 
   const uint32_t count = t.meta & kTileCountMask;
   const bool vec_ok = (t.meta & kTileVecBit) != 0;
   if constexpr (OP == 0) {
-    add_tile<W, S_WORDS, K, kTheta, kPhi, kKt, kAtom64>(fv, a.keys + t.key_start, count, vec_ok,
+    add_tile<W, S_WORDS, K, kTheta, kPhi, kKt, kAtom64>(fv, f.keys + t.key_start, count, vec_ok,
                                                         a.k, lp);
   } else {
-    contains_tile<W, S_WORDS, K, kTheta, kPhi, kKt>(fv, a.keys + t.key_start, a.out + t.key_start,
+    contains_tile<W, S_WORDS, K, kTheta, kPhi, kKt>(fv, f.keys + t.key_start, f.out + t.key_start,
                                                     count, vec_ok, a.k, lp);
   }
 }
@@ -82,9 +82,9 @@ __global__ __launch_bounds__(kBlockThreads) void bf_batch_kernel(BatchArgs a) {
     const BatchFilter f = a.filters[t.filter];
     const FilterView fv{f.words, f.hash_init, f.nb_lo, f.nb_hi_mask};
     switch ((t.meta >> kTileClassShift) & 3u) {
-      case 0: batch_tile<W, S_WORDS, K, OP, 0>(a, t, fv); break;
-      case 1: batch_tile<W, S_WORDS, K, OP, 1>(a, t, fv); break;
-      default: batch_tile<W, S_WORDS, K, OP, 2>(a, t, fv); break;
+      case 0: batch_tile<W, S_WORDS, K, OP, 0>(a, t, f, fv); break;
+      case 1: batch_tile<W, S_WORDS, K, OP, 1>(a, t, f, fv); break;
+      default: batch_tile<W, S_WORDS, K, OP, 2>(a, t, f, fv); break;
     }
   }
 }

@@ -192,6 +192,42 @@ __global__ __launch_bounds__(kThreads) void gups_kernel(uint64_t* buf, uint64_t 
   }
 }
 
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): element i of stream `seed`
+// is the output function applied to seed + (i + 1) * 0x9E3779B97F4A7C15.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ __launch_bounds__(kThreads) void splitmix_kernel(uint64_t* out, uint64_t n, uint64_t seed,
+                                                            uint64_t first) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kThreads;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride)
+    out[i] = splitmix64_at(seed, first + i);
+}
+
+// Query i: with probability hit_q32 / 2^32 element j of the source stream
+// (j uniform in [src_first, src_first + src_count)), else element
+// fresh_first + i of the fresh stream; the choice and j come from element i
+// of the mix stream.
+__global__ __launch_bounds__(kThreads) void mixed_query_kernel(uint64_t* out, uint64_t n,
+                                                               uint64_t src_seed, uint64_t src_first,
+                                                               uint32_t src_count,
+                                                               uint64_t fresh_seed,
+                                                               uint64_t fresh_first,
+                                                               uint32_t hit_q32, uint64_t mix_seed) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kThreads;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x; i < n; i += stride) {
+    const uint64_t r = splitmix64_at(mix_seed, i);
+    const uint32_t choose = static_cast<uint32_t>(r >> 32);
+    const uint32_t pick = __umulhi(static_cast<uint32_t>(r), src_count);
+    out[i] = choose < hit_q32 ? splitmix64_at(src_seed, src_first + pick)
+                              : splitmix64_at(fresh_seed, fresh_first + i);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void copy_kernel(u32x4* dst, const u32x4* src, uint64_t nvec) {
   const uint64_t i = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x;
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kThreads;
@@ -346,6 +382,25 @@ int bfb_gups(void* d_buf, uint64_t buf_bytes, uint64_t n_updates, uint32_t seed,
   hipLaunchKernelGGL(gups_kernel, dim3(grid_for(threads)), dim3(kThreads), 0,
                      static_cast<hipStream_t>(stream), static_cast<uint64_t*>(d_buf), n_updates, lo,
                      him, seed);
+  return hipGetLastError() == hipSuccess ? BFB_OK : BFB_EDEVICE;
+}
+
+int bfb_fill_splitmix64(uint64_t* d_out, uint64_t n, uint64_t seed, uint64_t first, void* stream) {
+  if (d_out == nullptr) return BFB_EINVAL;
+  if (n == 0) return BFB_OK;
+  hipLaunchKernelGGL(splitmix_kernel, dim3(grid_for(n < (1u << 24) ? n : (1u << 24))), dim3(kThreads),
+                     0, static_cast<hipStream_t>(stream), d_out, n, seed, first);
+  return hipGetLastError() == hipSuccess ? BFB_OK : BFB_EDEVICE;
+}
+
+int bfb_fill_mixed_queries(uint64_t* d_out, uint64_t n, uint64_t src_seed, uint64_t src_first,
+                           uint32_t src_count, uint64_t fresh_seed, uint64_t fresh_first,
+                           uint32_t hit_q32, uint64_t mix_seed, void* stream) {
+  if (d_out == nullptr || src_count == 0) return BFB_EINVAL;
+  if (n == 0) return BFB_OK;
+  hipLaunchKernelGGL(mixed_query_kernel, dim3(grid_for(n < (1u << 24) ? n : (1u << 24))),
+                     dim3(kThreads), 0, static_cast<hipStream_t>(stream), d_out, n, src_seed,
+                     src_first, src_count, fresh_seed, fresh_first, hit_q32, mix_seed);
   return hipGetLastError() == hipSuccess ? BFB_OK : BFB_EDEVICE;
 }
 

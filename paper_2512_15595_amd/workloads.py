@@ -165,3 +165,35 @@ def batched_workload(nfilters: int = 4096, total_keys: int = 2**28, lo_bytes: in
     take = g.random(owner.size) < 0.5
     queries = np.where(take, hits, fresh)
     return sizes, offsets, keys, queries
+
+
+SPLITMIX_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+
+
+def splitmix64(seed: int, first: int, n: int) -> np.ndarray:
+    """Elements first..first+n-1 of the SplitMix64 stream `seed` (Steele,
+    Lea, Flood 2014): the output function of seed + (i + 1) * gamma.  The
+    same definition runs on the device for workloads too large for the host
+    (bfb_fill_splitmix64)."""
+    with np.errstate(over="ignore"):
+        i = np.arange(first, first + n, dtype=np.uint64)
+        z = np.uint64(seed) + (i + np.uint64(1)) * SPLITMIX_GAMMA
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        return z ^ (z >> np.uint64(31))
+
+
+def mixed_queries(n: int, src_seed: int, src_first: int, src_count: int, fresh_seed: int,
+                  fresh_first: int, hit_fraction: float, mix_seed: int) -> np.ndarray:
+    """Host twin of bfb_fill_mixed_queries."""
+    hit_q32 = np.uint64(min(int(hit_fraction * 2**32), 2**32 - 1))
+    r = splitmix64(mix_seed, 0, n)
+    choose = r >> np.uint64(32)
+    pick = ((r & np.uint64(0xFFFFFFFF)) * np.uint64(src_count)) >> np.uint64(32)
+    with np.errstate(over="ignore"):
+        src = np.uint64(src_seed) + (np.uint64(src_first) + pick + np.uint64(1)) * SPLITMIX_GAMMA
+        z = (src ^ (src >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        hits = z ^ (z >> np.uint64(31))
+    fresh = splitmix64(fresh_seed, fresh_first, n)
+    return np.where(choose < hit_q32, hits, fresh)
