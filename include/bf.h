@@ -31,9 +31,11 @@
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is enqueued and the status says why.  Launch failures are BF_EDEVICE.
  *     Faults inside a kernel surface at the caller's next synchronization.
- *   - Concurrency: bf_add calls on one filter from several streams commute.
- *     A bf_contains that is not ordered after a bf_add (by stream order or
- *     events) sees some state between "before" and "after" that add.
+ *   - Concurrency: direct-strategy bf_add calls on one filter from several
+ *     streams commute; a partitioned-strategy add must be ordered against
+ *     other writers of the filter.  A bf_contains that is not ordered after
+ *     a bf_add (by stream order or events) may see any state between
+ *     "before" and "after" that add.
  */
 #ifndef BF_H
 #define BF_H
@@ -56,6 +58,12 @@ typedef int32_t bf_status;
 
 typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
 
+/* Construction strategies (bf_mapping_t.strategy, add only). */
+#define BF_STRATEGY_AUTO 0        /* partitioned for dense batches, else direct */
+#define BF_STRATEGY_DIRECT 1      /* one atomic OR group per key into the filter */
+#define BF_STRATEGY_PARTITIONED 2 /* keys grouped by filter chunk; each chunk is
+                                     updated in LDS and stored back */
+
 /* Execution mapping of one operation (Sec. IV-A and IV-C).  A field left 0
  * means "use the default for this layout".
  *   lanes_per_key   Theta: lanes cooperating on one key, power of two <= 16;
@@ -66,13 +74,23 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *                   words into one 64-bit atomic OR (needs Phi >= 2); 32 or
  *                   0 otherwise;
  *   max_workgroups  grid cap of the grid-stride launch (0 = one workgroup
- *                   per 256 * keys_per_lane keys). */
+ *                   per 256 * keys_per_lane keys);
+ *   strategy        add only: BF_STRATEGY_*.  The partitioned strategy
+ *                   radix-partitions the keys by 64 KiB filter chunk and
+ *                   updates each chunk in LDS, so a bulk add performs no
+ *                   global atomics; it uses a workspace of 16 bytes per key
+ *                   (allocated by the filter on first need, which
+ *                   synchronizes the device), and while it runs it owns the
+ *                   filter: another add on a different stream must be
+ *                   ordered against it (events).  Mapping fields other than
+ *                   strategy do not apply to it.  Results are identical. */
 typedef struct {
   uint32_t lanes_per_key;
   uint32_t words_per_lane;
   uint32_t keys_per_lane;
   uint32_t atomic_bits;
   uint32_t max_workgroups;
+  uint32_t strategy;
 } bf_mapping_t;
 
 typedef struct {

@@ -31,6 +31,9 @@ BF_EDEVICE = -3
 BF_EUNSUPPORTED = -4
 BF_OP_ADD = 0
 BF_OP_CONTAINS = 1
+BF_STRATEGY_AUTO = 0
+BF_STRATEGY_DIRECT = 1
+BF_STRATEGY_PARTITIONED = 2
 
 
 class bf_mapping_t(ctypes.Structure):
@@ -40,6 +43,7 @@ class bf_mapping_t(ctypes.Structure):
         ("keys_per_lane", ctypes.c_uint32),
         ("atomic_bits", ctypes.c_uint32),
         ("max_workgroups", ctypes.c_uint32),
+        ("strategy", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -216,8 +220,10 @@ def bf_set_mapping(f, op: int, lanes_per_key: int, words_per_lane: int, keys_per
 
 
 def bf_set_mapping_ex(f, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
-                      keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0) -> int:
-    m = bf_mapping_t(lanes_per_key, words_per_lane, keys_per_lane, atomic_bits, max_workgroups)
+                      keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0,
+                      strategy: int = 0) -> int:
+    m = bf_mapping_t(lanes_per_key, words_per_lane, keys_per_lane, atomic_bits, max_workgroups,
+                     strategy)
     return _lib.bf_set_mapping_ex(f, op, ctypes.byref(m))
 
 
@@ -335,9 +341,10 @@ class BloomFilter:
         return info
 
     def set_mapping(self, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
-                    keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0) -> None:
+                    keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0,
+                    strategy: int = 0) -> None:
         _check(bf_set_mapping_ex(self._h, op, lanes_per_key, words_per_lane, keys_per_lane,
-                                 atomic_bits, max_workgroups), "bf_set_mapping_ex")
+                                 atomic_bits, max_workgroups, strategy), "bf_set_mapping_ex")
 
     def words(self, stream=None):
         """A device copy of the words as a torch uint8 tensor."""

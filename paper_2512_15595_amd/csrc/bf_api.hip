@@ -83,8 +83,10 @@ bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     const uint32_t cap = m.max_workgroups;
     const uint32_t ab = m.atomic_bits;
+    const uint32_t strategy = m.strategy;
     m = default_mapping(f, op);
     m.max_workgroups = cap;
+    m.strategy = strategy;
     if (ab != 0 && op == BF_OP_ADD && f->word_bits == 32 && m.words_per_lane >= 2) m.atomic_bits = ab;
   }
   if (m.atomic_bits == 0) m.atomic_bits = 32;
@@ -99,6 +101,8 @@ bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
 }
 
 bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
+  if (m.strategy > BF_STRATEGY_PARTITIONED) return BF_EINVAL;
+  if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     // default mapping; only the atomic width may be forced
     if (m.atomic_bits != 0 && m.atomic_bits != 32 && m.atomic_bits != 64) return BF_EINVAL;
@@ -117,10 +121,22 @@ bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
   return BF_OK;
 }
 
-bf_status launch(const bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
+// Strategy of one bulk add: partitioned when asked for, or (auto) when the
+// batch is dense enough for streaming the touched chunks to beat one
+// memory-side atomic group per key.
+bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
+  if (m.strategy == BF_STRATEGY_DIRECT) return false;
+  if (!partition_applicable(f, n)) return false;
+  if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
+  return n >= (1ull << 20) && n >= f->nbytes / 64;
+}
+
+bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                  void* stream) {
   ensure_registry();
   bf_mapping_t m = resolve_mapping(f, op);
+  if (op == BF_OP_ADD && use_partitioned(f, n, f->mapping[BF_OP_ADD]))
+    return partitioned_add(f, keys, n, static_cast<hipStream_t>(stream));
   // Keys per lane needs 8*KT-byte aligned keys (and KT-byte aligned results);
   // fall back to fewer keys per lane otherwise.
   uint32_t kt = m.keys_per_lane;
@@ -221,6 +237,7 @@ bf_status bf_destroy(bf_filter* f) {
   bf_status st = BF_OK;
   if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
   if (hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
+  if (f->scratch != nullptr && hipFree(f->scratch) != hipSuccess) st = BF_EDEVICE;
   delete f;
   return st;
 }
@@ -238,7 +255,7 @@ bf_status bf_contains(const bf_filter* f, const uint64_t* d_keys, uint64_t n, ui
   if (n == 0) return BF_OK;
   if (d_keys == nullptr || d_out == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0)
     return BF_EINVAL;
-  return launch(f, BF_OP_CONTAINS, d_keys, n, d_out, stream);
+  return launch(const_cast<bf_filter*>(f), BF_OP_CONTAINS, d_keys, n, d_out, stream);
 }
 
 bf_status bf_clear(bf_filter* f, void* stream) {

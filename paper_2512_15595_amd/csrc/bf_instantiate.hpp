@@ -5,6 +5,7 @@
 
 #include "bf_batch_kernels.hpp"
 #include "bf_kernels.hpp"
+#include "bf_partition.hpp"
 #include "bf_registry.hpp"
 
 namespace bfhip {
@@ -62,6 +63,8 @@ void register_batch(Registry& r) {
         reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpAdd>);
     r.batch_fn[batch_index(kOpContains, kBits, S_WORDS, k_index(K))] =
         reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpContains>);
+    r.apply_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&part_apply_kernel<W, S_WORDS, K>);
   }
 }
 

@@ -56,6 +56,7 @@ constexpr int kBatchRegistrySize = 2 * 2 * kLog2Max * kNumK;
 struct Registry {
   const void* fn[kRegistrySize];
   const void* batch_fn[kBatchRegistrySize];  // persistent batched kernels
+  const void* apply_fn[kBatchRegistrySize];  // partitioned-add apply kernels (op slot 0)
 };
 
 Registry& registry();

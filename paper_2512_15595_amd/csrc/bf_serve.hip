@@ -141,13 +141,17 @@ void finish_request(bf_server* s, uint64_t id, uint64_t admit, uint64_t complete
 bool launch_group(bf_server* s, const std::vector<Pending>& group, uint64_t group_bytes) {
   StreamCtx& sc = s->streams[s->next_stream++ % s->streams.size()];
   const int op = static_cast<int>(group[0].r.op);
-  // dependencies: contains after earlier adds, add after earlier contains
+  // dependencies: contains after earlier adds; add after earlier contains
+  // and earlier adds (a partitioned add owns its filter while it runs)
   std::vector<hipEvent_t> waits;
-  for (const Pending& p : group) {
-    const FilterDeps& d = s->deps[p.r.filter];
-    const std::vector<hipEvent_t>& src = op == BF_OP_CONTAINS ? d.adds : d.reads;
+  auto wait_on = [&waits](const std::vector<hipEvent_t>& src) {
     for (hipEvent_t e : src)
       if (std::find(waits.begin(), waits.end(), e) == waits.end()) waits.push_back(e);
+  };
+  for (const Pending& p : group) {
+    const FilterDeps& d = s->deps[p.r.filter];
+    wait_on(d.adds);
+    if (op == BF_OP_ADD) wait_on(d.reads);
   }
   for (hipEvent_t e : waits)
     if (hipStreamWaitEvent(sc.s, e, 0) != hipSuccess) return false;

@@ -185,3 +185,60 @@ def test_bad_mapping_is_rejected():
         assert info.mapping[bf.BF_OP_ADD].lanes_per_key >= 1
     finally:
         f.close()
+
+
+@pytest.mark.parametrize("s,S", LAYOUTS)
+def test_partitioned_add_bit_exact(s, S):
+    """The partitioned construction (keys grouped by 64 KiB chunk, chunks
+    updated in LDS) writes exactly the oracle's words: a block count that
+    leaves the last chunk partial, ragged key counts, compiled and runtime k."""
+    bf = _bf()
+    block = s * S // 8
+    for nblocks, nkeys, k in ((3 * (65536 // block) + 17, 100_003, 16 if s == 16 else 8),
+                              (7, 5_000, max(s, 5)),
+                              (200_001, 333_333, max(s, 12))):
+        params = dict(num_blocks=nblocks, words_per_block=s, word_bits=S, k=k, seed=nblocks)
+        g = workloads.rng(nblocks + s)
+        adds = g.integers(0, 2**64, size=nkeys, dtype=np.uint64)
+        queries = np.concatenate([adds[:2000], g.integers(0, 2**64, size=3000, dtype=np.uint64)])
+        log(f"partitioned s={s} S={S} blocks={nblocks} keys={nkeys} k={k}")
+        want_words, want_out = _oracle(params, adds, queries)
+        f = bf.BloomFilter(**params)
+        try:
+            f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+            f.add(to_device(adds))
+            assert np.array_equal(f.words().cpu().numpy(), want_words)
+            assert np.array_equal(f.contains(to_device(queries)).cpu().numpy(), want_out)
+            # a second batch on top (workspace reuse, smaller)
+            more = g.integers(0, 2**64, size=nkeys // 3 + 1, dtype=np.uint64)
+            f.add(to_device(more))
+            ref = oracle.OracleFilter(**params)
+            ref.add(adds)
+            ref.add(more)
+            assert np.array_equal(f.words().cpu().numpy(), ref.bytes)
+            torch.cuda.synchronize()
+        finally:
+            f.close()
+
+
+def test_auto_strategy_matches_direct():
+    """Auto picks the partitioned path for a dense batch; words equal those
+    of the direct path."""
+    bf = _bf()
+    params = dict(num_blocks=1 << 20, words_per_block=8, word_bits=32, k=8, seed=3)
+    adds = workloads.uniform_keys(1 << 21, 17)
+    d = to_device(adds)
+    words = {}
+    for strategy in (bf.BF_STRATEGY_AUTO, bf.BF_STRATEGY_DIRECT, bf.BF_STRATEGY_PARTITIONED):
+        f = bf.BloomFilter(**params)
+        try:
+            f.set_mapping(bf.BF_OP_ADD, strategy=strategy)
+            f.add(d)
+            words[strategy] = f.words().cpu().numpy()
+        finally:
+            f.close()
+    assert np.array_equal(words[0], words[1]) and np.array_equal(words[1], words[2])
+    sel = workloads.rng(4).choice(params["num_blocks"], size=4096, replace=False).astype(np.uint64)
+    want = oracle.block_words(params["num_blocks"], 8, 32, 8, 3, adds, sel)
+    rows = words[0].reshape(params["num_blocks"], -1)[sel.astype(np.int64)]
+    assert np.array_equal(rows, want)
