@@ -122,13 +122,17 @@ bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
 }
 
 // Strategy of one bulk add: partitioned when asked for, or (auto) when the
-// batch is dense enough for streaming the touched chunks to beat one
-// memory-side atomic group per key.
+// filter has enough 64 KiB chunks to occupy every CU (one workgroup owns a
+// chunk) and the batch is dense enough for streaming the touched chunks to
+// beat one memory-side atomic group per key (~40 B of record traffic per
+// key plus two passes over the filter, against ~50 ps per key of atomic
+// request rate).
 bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
   if (m.strategy == BF_STRATEGY_DIRECT) return false;
   if (!partition_applicable(f, n)) return false;
   if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
-  return n >= (1ull << 20) && n >= f->nbytes / 64;
+  const uint64_t chunks = f->nbytes / (64 * 1024);
+  return chunks >= 512 && n >= (1ull << 21) && n >= f->nbytes / 48;
 }
 
 bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,

@@ -63,6 +63,10 @@ void register_batch(Registry& r) {
         reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpAdd>);
     r.batch_fn[batch_index(kOpContains, kBits, S_WORDS, k_index(K))] =
         reinterpret_cast<const void*>(&bf_batch_kernel<W, S_WORDS, K, kOpContains>);
+    r.part1_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K>);
+    r.part2_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&part_scatter2_kernel<W, S_WORDS, K>);
     r.apply_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
         reinterpret_cast<const void*>(&part_apply_kernel<W, S_WORDS, K>);
   }

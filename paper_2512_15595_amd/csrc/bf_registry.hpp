@@ -56,7 +56,9 @@ constexpr int kBatchRegistrySize = 2 * 2 * kLog2Max * kNumK;
 struct Registry {
   const void* fn[kRegistrySize];
   const void* batch_fn[kBatchRegistrySize];  // persistent batched kernels
-  const void* apply_fn[kBatchRegistrySize];  // partitioned-add apply kernels (op slot 0)
+  const void* part1_fn[kBatchRegistrySize];  // partitioned add: first scatter (op slot 0)
+  const void* part2_fn[kBatchRegistrySize];  // partitioned add: second scatter
+  const void* apply_fn[kBatchRegistrySize];  // partitioned add: per-chunk apply
 };
 
 Registry& registry();
