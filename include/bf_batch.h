@@ -12,6 +12,15 @@
  * keys per lane) by the filter's size class from the autotuned table, and
  * records one persistent kernel launch in a HIP graph.
  *
+ * An add plan whose keys are dense enough over its filters (the rule of
+ * BF_STRATEGY_AUTO in bf.h, applied to all filters together) is instead
+ * planned as one partitioned construction over every filter: the filters'
+ * blocks are laid end to end in one block space, one radix partition
+ * groups all keys by 64 KiB chunk, and each chunk is updated in LDS (four
+ * kernels in the graph).  Filter 0's add strategy (bf_set_mapping_ex) can
+ * force BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED.  The partitioned
+ * plan owns its filters while it runs, like a partitioned bf_add.
+ *
  * All filters of a plan must share words_per_block, word_bits and k.  Keys
  * of filter i are d_keys[h_offsets[i] .. h_offsets[i+1]) (device memory,
  * one concatenated array); lookup results go to d_out at the same offsets.
@@ -39,9 +48,10 @@ typedef struct {
   uint32_t nfilters;
   uint64_t nkeys;          /* h_offsets[nfilters] - h_offsets[0] */
   uint64_t ntiles;         /* tile slots in the launch (including padding) */
-  uint32_t grid;           /* workgroups of the persistent launch */
+  uint32_t grid;           /* workgroups of the persistent launch (first pass if partitioned) */
   uint32_t tiles_per_class[3]; /* L2 / Infinity-Cache / HBM sized filters */
   bf_mapping_t mapping[3]; /* mapping compiled in per size class */
+  uint32_t strategy;       /* BF_STRATEGY_DIRECT (tiles) or BF_STRATEGY_PARTITIONED */
 } bf_batch_info_t;
 
 /* Plans one batched operation (op = BF_OP_ADD or BF_OP_CONTAINS) over

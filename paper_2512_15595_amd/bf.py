@@ -94,6 +94,7 @@ class bf_batch_info_t(ctypes.Structure):
         ("grid", ctypes.c_uint32),
         ("tiles_per_class", ctypes.c_uint32 * 3),
         ("mapping", bf_mapping_t * 3),
+        ("strategy", ctypes.c_uint32),
     ]
 
 

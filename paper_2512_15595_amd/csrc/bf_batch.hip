@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -10,6 +11,7 @@
 #include "../../include/bf_batch.h"
 #include "bf_batch_kernels.hpp"
 #include "bf_internal.hpp"
+#include "bf_partition.hpp"
 #include "bf_registry.hpp"
 #include "bf_tuned.hpp"
 
@@ -40,6 +42,12 @@ struct bf_batch {
   BatchArgs args;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  // partitioned construction over all filters of the plan (add only)
+  bool partitioned;
+  PartArgs part;
+  PartLayout part_layout;
+  PartKernels part_k;
+  void* part_scratch;
 };
 
 namespace {
@@ -54,7 +62,197 @@ void free_plan(bf_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->d_filters) (void)hipFree(b->d_filters);
   if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->part_scratch) (void)hipFree(b->part_scratch);
   delete b;
+}
+
+// Partitioned construction for a whole add plan: the filters' blocks are
+// laid end to end in one global block space (each filter starting on a
+// chunk boundary), so one radix partition groups every key of every filter
+// by global chunk.  Returns BF_OK and sets b->partitioned when taken.
+bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfilters,
+                           const uint64_t* d_keys, const uint64_t* h_offsets) {
+  const bf_filter* f0 = filters[0];
+  const uint32_t strategy = f0->mapping[BF_OP_ADD].strategy;
+  if (strategy == BF_STRATEGY_DIRECT) return BF_OK;
+  const uint32_t shift = part_chunk_shift(f0->s, f0->word_bits);
+  const uint64_t bpc = 1ull << shift;
+  std::vector<PartFilter> pf(nfilters);
+  uint64_t chunks = 0, total_bytes = 0;
+  for (uint32_t i = 0; i < nfilters; ++i) {
+    const bf_filter* f = filters[i];
+    pf[i].words = f->d_words;
+    pf[i].hash_init = xxh64_u64_init(f->seed);
+    pf[i].nb_lo = static_cast<uint32_t>(f->num_blocks);
+    pf[i].nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
+    pf[i].num_blocks = f->num_blocks;
+    pf[i].chunk_base = chunks;
+    pf[i].block_base = chunks * bpc;
+    pf[i].key_begin = h_offsets[i] - h_offsets[0];
+    pf[i].key_end = h_offsets[i + 1] - h_offsets[0];
+    chunks += (f->num_blocks + bpc - 1) / bpc;
+    total_bytes += f->nbytes;
+  }
+  const uint64_t n = h_offsets[nfilters] - h_offsets[0];
+  if (n == 0 || chunks * bpc > (1ull << 32)) return BF_OK;  // global blocks must fit 32 bits
+  if (strategy == BF_STRATEGY_AUTO &&
+      !(chunks >= 512 && n >= (1ull << 21) && n >= total_bytes / 48))
+    return BF_OK;
+  PartArgs a{};
+  PartLayout L{};
+  if (!part_geometry(chunks, shift, n, a, L)) return BF_OK;
+  const PartKernels k = part_kernels(f0);
+  if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_OK;
+  // Per-bucket capacities from each chunk's expected load: filter i's keys
+  // spread uniformly over its blocks (a chunk holding part of the filter
+  // expects that part's share); six standard deviations plus a margin.
+  std::vector<double> load(chunks, 0.0);
+  for (uint32_t i = 0; i < nfilters; ++i) {
+    const double ni = static_cast<double>(pf[i].key_end - pf[i].key_begin);
+    if (ni == 0) continue;
+    const uint64_t nc = (pf[i].num_blocks + bpc - 1) / bpc;
+    for (uint64_t c = 0; c < nc; ++c) {
+      const uint64_t blocks = std::min<uint64_t>(bpc, pf[i].num_blocks - c * bpc);
+      load[pf[i].chunk_base + c] = ni * static_cast<double>(blocks) / static_cast<double>(pf[i].num_blocks);
+    }
+  }
+  auto cap_of = [](double mean, double margin) {
+    if (mean <= 0.0) return uint64_t{0};
+    return static_cast<uint64_t>(std::ceil(mean + 6.0 * std::sqrt(mean) + margin));
+  };
+  std::vector<uint64_t> off1(a.f1 + 1, 0), off2(chunks + 1, 0);
+  for (uint64_t c = 0; c < chunks; ++c) off2[c + 1] = off2[c] + cap_of(load[c], 64.0);
+  for (uint32_t d = 0; d < a.f1; ++d) {
+    double m = 0.0;
+    for (uint64_t c = static_cast<uint64_t>(d) * a.f2; c < std::min<uint64_t>(chunks, (d + 1ull) * a.f2); ++c)
+      m += load[c];
+    off1[d + 1] = off1[d] + cap_of(m, 1024.0);
+  }
+  // buffers sized by the extents (replacing the uniform layout)
+  L.off_buf1 = 0;
+  L.off_buf2 = (8 * off1[a.f1] + 255) & ~255ull;
+  L.off_fill = (L.off_buf2 + 8 * off2[chunks] + 255) & ~255ull;
+  L.total = (L.off_fill + 8 * L.nfill + 255) & ~255ull;
+  // tables after the buffers: filters, chunk owners, first filter per
+  // first-pass workgroup
+  std::vector<uint32_t> owner(chunks);
+  for (uint32_t i = 0; i < nfilters; ++i) {
+    const uint64_t c_end = i + 1 < nfilters ? pf[i + 1].chunk_base : chunks;
+    std::fill(owner.begin() + static_cast<std::ptrdiff_t>(pf[i].chunk_base),
+              owner.begin() + static_cast<std::ptrdiff_t>(c_end), i);
+  }
+  const uint32_t g1 = part_grid1(a).x;
+  std::vector<uint32_t> first(g1);
+  for (uint32_t g = 0; g < g1; ++g) {
+    const uint64_t begin = static_cast<uint64_t>(g) * a.range1;
+    uint32_t lo = 0, hi = nfilters - 1;  // first filter with key_end > begin
+    while (lo < hi) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (pf[mid].key_end > begin) hi = mid; else lo = mid + 1;
+    }
+    first[g] = lo;
+  }
+  const uint64_t off_pf = L.total;
+  const uint64_t off_owner = (off_pf + pf.size() * sizeof(PartFilter) + 255) & ~255ull;
+  const uint64_t off_first = (off_owner + owner.size() * 4 + 255) & ~255ull;
+  // work lists: heavily loaded buckets are split over several workgroups
+  // (~64K records per second-pass slice; ~128K per apply slice, each of
+  // which then merges its whole chunk image with atomics)
+  std::vector<PartWork> work2, work3;
+  for (uint32_t d = 0; d < a.f1; ++d) {
+    const uint64_t ns = std::clamp<uint64_t>((off1[d + 1] - off1[d] + 65535) / 65536, 1, 65535);
+    for (uint64_t i = 0; i < ns; ++i)
+      work2.push_back(PartWork{d, static_cast<uint16_t>(i), static_cast<uint16_t>(ns)});
+  }
+  for (uint64_t c = 0; c < chunks; ++c) {
+    const uint64_t ns = std::clamp<uint64_t>(static_cast<uint64_t>(load[c] / 131072.0) + 1, 1, 65535);
+    for (uint64_t i = 0; i < ns; ++i)
+      work3.push_back(PartWork{static_cast<uint32_t>(c), static_cast<uint16_t>(i), static_cast<uint16_t>(ns)});
+  }
+  const uint64_t off_ext1 = (off_first + first.size() * 4 + 255) & ~255ull;
+  const uint64_t off_ext2 = (off_ext1 + off1.size() * 8 + 255) & ~255ull;
+  const uint64_t off_w2 = (off_ext2 + off2.size() * 8 + 255) & ~255ull;
+  const uint64_t off_w3 = (off_w2 + work2.size() * sizeof(PartWork) + 255) & ~255ull;
+  const uint64_t total = (off_w3 + work3.size() * sizeof(PartWork) + 255) & ~255ull;
+  if (work2.size() > 0xffffffffull || work3.size() > 0xffffffffull) return BF_OK;
+  if (hipMalloc(&b->part_scratch, total) != hipSuccess) {
+    (void)hipGetLastError();
+    b->part_scratch = nullptr;
+    return BF_ENOMEM;
+  }
+  uint8_t* base = static_cast<uint8_t*>(b->part_scratch);
+  if (hipMemcpy(base + off_pf, pf.data(), pf.size() * sizeof(PartFilter), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(base + off_owner, owner.data(), owner.size() * 4, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(base + off_first, first.data(), first.size() * 4, hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(base + off_ext1, off1.data(), off1.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + off_ext2, off2.data(), off2.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(base + off_w2, work2.data(), work2.size() * sizeof(PartWork), hipMemcpyHostToDevice) !=
+          hipSuccess ||
+      hipMemcpy(base + off_w3, work3.data(), work3.size() * sizeof(PartWork), hipMemcpyHostToDevice) !=
+          hipSuccess)
+    return BF_EDEVICE;
+  part_bind(a, L, b->part_scratch);
+  a.off1 = reinterpret_cast<const uint64_t*>(base + off_ext1);
+  a.off2 = reinterpret_cast<const uint64_t*>(base + off_ext2);
+  a.work2 = reinterpret_cast<const PartWork*>(base + off_w2);
+  a.nwork2 = static_cast<uint32_t>(work2.size());
+  a.work3 = reinterpret_cast<const PartWork*>(base + off_w3);
+  a.nwork3 = static_cast<uint32_t>(work3.size());
+  a.words = pf[0].words;  // the single-filter fields mirror filter 0
+  a.num_blocks = pf[0].num_blocks;
+  a.hash_init = pf[0].hash_init;
+  a.nb_lo = pf[0].nb_lo;
+  a.nb_hi_mask = pf[0].nb_hi_mask;
+  a.filters = reinterpret_cast<const PartFilter*>(base + off_pf);
+  a.chunk_owner = reinterpret_cast<const uint32_t*>(base + off_owner);
+  a.wg_first = reinterpret_cast<const uint32_t*>(base + off_first);
+  a.nfilters = nfilters;
+  a.k = f0->k;
+  a.keys = d_keys + h_offsets[0];
+  b->part = a;
+  b->part_layout = L;
+  b->part_k = k;
+  b->partitioned = true;
+  return BF_OK;
+}
+
+bf_status build_partitioned_graph(bf_batch* b) {
+  hipGraphNode_t prev = nullptr, node = nullptr;
+  unsigned long long* fills = b->part.fill1;
+  uint64_t nfill = b->part_layout.nfill;
+  void* zargs[] = {&fills, &nfill};
+  void* pargs[] = {&b->part};
+  struct Step {
+    const void* fn;
+    dim3 grid, block;
+    void** args;
+  } steps[] = {
+      {reinterpret_cast<const void*>(&part_zero_kernel),
+       dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>((nfill + 255) / 256, 4096)))),
+       dim3(kPartThreads), zargs},
+      {b->part_k.scatter1, part_grid1(b->part), dim3(kPartThreads), pargs},
+      {b->part_k.scatter2, part_grid2(b->part), dim3(kPartThreads), pargs},
+      {b->part_k.apply, part_grid3(b->part), dim3(kApplyThreads), pargs},
+  };
+  if (hipGraphCreate(&b->graph, 0) != hipSuccess) return BF_EDEVICE;
+  for (const Step& st : steps) {
+    hipKernelNodeParams p{};
+    p.func = const_cast<void*>(st.fn);
+    p.gridDim = st.grid;
+    p.blockDim = st.block;
+    p.sharedMemBytes = 0;
+    p.kernelParams = st.args;
+    p.extra = nullptr;
+    if (hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) !=
+        hipSuccess)
+      return BF_EDEVICE;
+    prev = node;
+  }
+  return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess ? BF_OK
+                                                                                     : BF_EDEVICE;
 }
 
 }  // namespace
@@ -96,6 +294,25 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   b->d_keys = d_keys;
   b->d_out = d_out;
   b->fn = fn;
+
+  if (op == BF_OP_ADD) {
+    bf_status pst = plan_partitioned(b, filters, nfilters, d_keys, h_offsets);
+    if (pst != BF_OK) {
+      free_plan(b);
+      return pst;
+    }
+    if (b->partitioned) {
+      b->ntiles = 0;
+      b->grid = part_grid1(b->part).x;
+      if (build_partitioned_graph(b) != BF_OK) {
+        (void)hipGetLastError();
+        free_plan(b);
+        return BF_EDEVICE;
+      }
+      *out = b;
+      return BF_OK;
+    }
+  }
 
   // Mapping per size class (identical for all filters of a class).
   for (int c = 0; c < kNumSizeClasses; ++c) {
@@ -210,13 +427,15 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
 
 bf_status bf_batch_launch(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
-  if (b->ntiles == 0) return BF_OK;
+  if (b->ntiles == 0 && !b->partitioned) return BF_OK;
   return hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? BF_OK
                                                                                   : BF_EDEVICE;
 }
 
 bf_status bf_batch_launch_direct(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
+  if (b->partitioned)
+    return part_launch(b->part, b->part_layout, b->part_k, static_cast<hipStream_t>(stream));
   if (b->ntiles == 0) return BF_OK;
   void* kargs[] = {&b->args};
   return hipLaunchKernel(b->fn, dim3(b->grid), dim3(kBlockThreads), kargs, 0,
@@ -247,6 +466,7 @@ bf_status bf_batch_info(const bf_batch* b, bf_batch_info_t* out) {
   i.nkeys = b->nkeys;
   i.ntiles = b->ntiles;
   i.grid = b->grid;
+  i.strategy = b->partitioned ? BF_STRATEGY_PARTITIONED : BF_STRATEGY_DIRECT;
   for (int c = 0; c < kNumSizeClasses; ++c) {
     i.tiles_per_class[c] = b->tiles_per_class[c];
     i.mapping[c] = b->mapping[c];

@@ -23,6 +23,24 @@ struct bf_filter {
 
 namespace bfhip {
 // Partitioned construction (bf_partition.hip).
+struct PartArgs;
+struct PartLayout {
+  uint64_t off_buf1, off_buf2, off_fill, nfill, total;
+};
+struct PartKernels {
+  const void* scatter1;
+  const void* scatter2;
+  const void* apply;
+};
 bool partition_applicable(const bf_filter* f, uint64_t n);
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream);
+uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits);
+bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L);
+void part_bind(PartArgs& a, const PartLayout& L, void* base);
+PartKernels part_kernels(const bf_filter* f);
+bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k, hipStream_t stream);
+dim3 part_grid1(const PartArgs& a);
+dim3 part_grid2(const PartArgs& a);
+dim3 part_grid3(const PartArgs& a);
+__global__ void part_zero_kernel(unsigned long long* p, uint64_t n);
 }  // namespace bfhip

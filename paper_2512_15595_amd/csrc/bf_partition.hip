@@ -1,6 +1,6 @@
 // bf_partition.hip -- host side of partitioned construction: geometry,
 // bucket capacities, workspace and the launch sequence (kernels in
-// bf_partition.hpp).
+// bf_partition.hpp), for one filter and for a table of filters.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -12,13 +12,13 @@
 
 namespace bfhip {
 
-namespace {
-
 __global__ __launch_bounds__(kPartThreads) void part_zero_kernel(unsigned long long* p, uint64_t n) {
   const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kPartThreads;
   for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kPartThreads + threadIdx.x; i < n; i += stride)
     p[i] = 0;
 }
+
+namespace {
 
 uint64_t align256(uint64_t v) { return (v + 255) & ~255ull; }
 
@@ -36,62 +36,99 @@ uint64_t capacity(double mean, uint64_t margin, uint64_t align) {
   return (v + align - 1) / align * align;
 }
 
-struct Layout {
-  PartArgs a;
-  uint64_t off_buf1, off_buf2, off_fill, nfill, total;
-};
+}  // namespace
 
-bool make_layout(const bf_filter* f, uint64_t n, Layout& L) {
-  const uint64_t block_bytes = static_cast<uint64_t>(f->s) * f->word_bits / 8;
-  const uint64_t bpc = kChunkBytes / block_bytes;
-  PartArgs a{};
-  while ((1ull << a.chunk_shift) < bpc) ++a.chunk_shift;
-  a.chunks = (f->num_blocks + bpc - 1) / bpc;
-  a.f2 = ceil_pow2(a.chunks) < 128 ? ceil_pow2(a.chunks) : 128;
+uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits) {
+  const uint64_t bpc = kChunkBytes / (static_cast<uint64_t>(words_per_block) * word_bits / 8);
+  uint32_t shift = 0;
+  while ((1ull << shift) < bpc) ++shift;
+  return shift;
+}
+
+bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L) {
+  a.chunk_shift = chunk_shift;
+  a.chunks = chunks;
+  // digits balanced between the passes: f2 ~ sqrt(chunks)
+  const uint64_t root = static_cast<uint64_t>(std::ceil(std::sqrt(static_cast<double>(chunks))));
+  a.f2 = std::min<uint32_t>(ceil_pow2(std::max<uint64_t>(root, 1)), 512);
+  a.low_bits = 0;
   while ((1u << a.low_bits) < a.f2) ++a.low_bits;
-  const uint64_t f1 = (a.chunks + a.f2 - 1) / a.f2;
-  if (f1 > static_cast<uint64_t>(kMaxDigits)) return false;
+  const uint64_t f1 = (chunks + a.f2 - 1) / a.f2;
+  if (f1 > static_cast<uint64_t>(kMaxDigits) || chunks == 0) return false;
   a.f1 = static_cast<uint32_t>(f1);
   a.n = n;
   uint64_t range = (n + 1023) / 1024;
   range = (range + kPartStep - 1) / kPartStep * kPartStep;
   a.range1 = std::max<uint64_t>(range, kPartStep);
-  // chunk buckets are filled uniformly (the last chunk may be partial)
   a.cap1 = capacity(static_cast<double>(n) / a.f1, 4 * kPartStep, 64);
-  a.cap2 = capacity(static_cast<double>(n) / a.chunks, 64, 16);
+  a.cap2 = capacity(static_cast<double>(n) / chunks, 64, 16);
   const uint64_t per_bucket = std::min<uint64_t>(a.cap1, n);
-  uint64_t q = (per_bucket + 65535) / 65536;
-  a.q = static_cast<uint32_t>(std::clamp<uint64_t>(q, 1, 32));
-  L.a = a;
+  a.q = static_cast<uint32_t>(std::clamp<uint64_t>((per_bucket + 65535) / 65536, 1, 32));
   uint64_t off = 0;
   L.off_buf1 = off;
   off = align256(off + 8ull * a.f1 * a.cap1);
   L.off_buf2 = off;
-  off = align256(off + 8ull * a.chunks * a.cap2);
+  off = align256(off + 8ull * chunks * a.cap2);
   L.off_fill = off;
-  L.nfill = a.f1 + a.chunks;
+  L.nfill = a.f1 + chunks;
   off = align256(off + 8ull * L.nfill);
   L.total = off;
   return true;
 }
 
-}  // namespace
-
-bool partition_applicable(const bf_filter* f, uint64_t n) {
-  Layout L;
-  return n > 0 && n < (1ull << 40) && make_layout(f, 1, L);
+void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
+  uint8_t* base = static_cast<uint8_t*>(base_ptr);
+  a.buf1 = reinterpret_cast<uint64_t*>(base + L.off_buf1);
+  a.buf2 = reinterpret_cast<uint64_t*>(base + L.off_buf2);
+  a.fill1 = reinterpret_cast<unsigned long long*>(base + L.off_fill);
+  a.fill2 = a.fill1 + a.f1;
 }
 
-bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
-  Layout L;
-  if (!make_layout(f, n, L)) return BF_EUNSUPPORTED;
+PartKernels part_kernels(const bf_filter* f) {
   ensure_registry();
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
-  const void* k1 = registry().part1_fn[idx];
-  const void* k2 = registry().part2_fn[idx];
-  const void* k3 = registry().apply_fn[idx];
-  if (k1 == nullptr || k2 == nullptr || k3 == nullptr) return BF_EUNSUPPORTED;
+  return PartKernels{registry().part1_fn[idx], registry().part2_fn[idx], registry().apply_fn[idx]};
+}
+
+bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k,
+                      hipStream_t stream) {
+  if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_EUNSUPPORTED;
+  const uint64_t zgrid = std::min<uint64_t>((L.nfill + kPartThreads - 1) / kPartThreads, 4096);
+  hipLaunchKernelGGL(part_zero_kernel, dim3(static_cast<uint32_t>(std::max<uint64_t>(zgrid, 1))),
+                     dim3(kPartThreads), 0, stream, a.fill1, L.nfill);
+  PartArgs copy = a;
+  void* args[] = {&copy};
+  if (hipLaunchKernel(k.scatter1, part_grid1(a), dim3(kPartThreads), args, 0, stream) != hipSuccess ||
+      hipLaunchKernel(k.scatter2, part_grid2(a), dim3(kPartThreads), args, 0, stream) != hipSuccess ||
+      hipLaunchKernel(k.apply, part_grid3(a), dim3(kApplyThreads), args, 0, stream) != hipSuccess)
+    return BF_EDEVICE;
+  return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
+}
+
+dim3 part_grid1(const PartArgs& a) { return dim3(static_cast<uint32_t>((a.n + a.range1 - 1) / a.range1)); }
+dim3 part_grid2(const PartArgs& a) { return dim3(a.work2 ? a.nwork2 : a.f1 * a.q); }
+dim3 part_grid3(const PartArgs& a) {
+  const uint64_t items = a.work3 ? a.nwork3 : a.chunks;
+  return dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, 65535))));
+}
+
+bool partition_applicable(const bf_filter* f, uint64_t n) {
+  PartArgs a{};
+  PartLayout L{};
+  const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
+  const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
+  return n > 0 && n < (1ull << 40) && part_geometry(chunks, shift, 1, a, L);
+}
+
+bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
+  PartArgs a{};
+  PartLayout L{};
+  const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
+  const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
+  if (!part_geometry(chunks, shift, n, a, L)) return BF_EUNSUPPORTED;
+  const PartKernels k = part_kernels(f);
+  if (k.scatter1 == nullptr) return BF_EUNSUPPORTED;
   if (f->scratch_bytes < L.total) {
     if (f->scratch != nullptr) {
       if (hipFree(f->scratch) != hipSuccess) return BF_EDEVICE;
@@ -105,33 +142,16 @@ bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStr
     }
     f->scratch_bytes = L.total;
   }
-  uint8_t* base = static_cast<uint8_t*>(f->scratch);
-  PartArgs a = L.a;
+  part_bind(a, L, f->scratch);
   a.words = f->d_words;
   a.num_blocks = f->num_blocks;
   a.hash_init = xxh64_u64_init(f->seed);
   a.nb_lo = static_cast<uint32_t>(f->num_blocks);
   a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
+  a.nfilters = 1;
   a.k = f->k;
   a.keys = keys;
-  a.buf1 = reinterpret_cast<uint64_t*>(base + L.off_buf1);
-  a.buf2 = reinterpret_cast<uint64_t*>(base + L.off_buf2);
-  a.fill1 = reinterpret_cast<unsigned long long*>(base + L.off_fill);
-  a.fill2 = a.fill1 + a.f1;
-
-  const uint64_t zgrid = std::min<uint64_t>((L.nfill + kPartThreads - 1) / kPartThreads, 4096);
-  hipLaunchKernelGGL(part_zero_kernel, dim3(static_cast<uint32_t>(std::max<uint64_t>(zgrid, 1))),
-                     dim3(kPartThreads), 0, stream, a.fill1, L.nfill);
-  void* args[] = {&a};
-  const uint64_t g1 = (n + a.range1 - 1) / a.range1;
-  const uint64_t g3 = std::min<uint64_t>(a.chunks, 65535);
-  if (hipLaunchKernel(k1, dim3(static_cast<uint32_t>(g1)), dim3(kPartThreads), args, 0, stream) !=
-          hipSuccess ||
-      hipLaunchKernel(k2, dim3(a.f1 * a.q), dim3(kPartThreads), args, 0, stream) != hipSuccess ||
-      hipLaunchKernel(k3, dim3(static_cast<uint32_t>(g3)), dim3(kApplyThreads), args, 0, stream) !=
-          hipSuccess)
-    return BF_EDEVICE;
-  return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
+  return part_launch(a, L, k, stream);
 }
 
 }  // namespace bfhip

@@ -39,14 +39,36 @@ constexpr int kPartPer = 16;                        // records per thread per st
 constexpr int kPartStep = kPartThreads * kPartPer;  // records per LDS-staged step
 constexpr int kApplyThreads = 1024;                 // apply: 16 waves share one chunk
 constexpr int kChunkBytes = 64 * 1024;              // LDS bytes owned per chunk
-constexpr int kMaxDigits = 512;                     // digit fan-out limit of one pass
+constexpr int kMaxDigits = 1024;                    // digit fan-out limit of one pass
+
+// One filter of a multi-filter partitioned add.  Its blocks occupy global
+// blocks [block_base, block_base + num_blocks) and its chunks global chunks
+// from chunk_base (block_base is a multiple of the blocks per chunk); its
+// keys are keys[key_begin, key_end).
+struct PartFilter {
+  void* words;
+  uint64_t hash_init;
+  uint32_t nb_lo;
+  uint32_t nb_hi_mask;
+  uint64_t num_blocks;
+  uint64_t block_base;
+  uint64_t chunk_base;
+  uint64_t key_begin;
+  uint64_t key_end;
+};
 
 struct PartArgs {
+  // the single filter (nfilters == 1) ...
   void* words;
   uint64_t num_blocks;
   uint64_t hash_init;
   uint32_t nb_lo;
   uint32_t nb_hi_mask;
+  // ... or a table of filters (nfilters > 1) sharing one layout and k
+  const PartFilter* filters;
+  const uint32_t* chunk_owner;  // global chunk -> filter
+  const uint32_t* wg_first;     // first filter of each first-pass workgroup's keys
+  uint32_t nfilters;
   uint32_t k;
   uint32_t chunk_shift;  // log2(blocks per chunk)
   uint32_t low_bits;     // bits of the low (second-pass) digit
@@ -57,27 +79,71 @@ struct PartArgs {
   const uint64_t* keys;
   uint64_t n;
   uint64_t range1;       // keys per first-pass workgroup (multiple of kPartStep)
-  uint64_t* buf1;        // f1 buckets of cap1 records
+  uint64_t* buf1;        // f1 buckets of cap1 records (or per off1)
   unsigned long long* fill1;
   uint64_t cap1;
-  uint64_t* buf2;        // chunk buckets of cap2 records
+  uint64_t* buf2;        // chunk buckets of cap2 records (or per off2)
   unsigned long long* fill2;
   uint64_t cap2;
+  // optional per-bucket extents (multi-filter plans, whose chunks expect
+  // different loads): bucket d spans [off[d], off[d + 1]) of its buffer
+  const uint64_t* off1;
+  const uint64_t* off2;
+  // optional work lists splitting heavily loaded buckets over several
+  // workgroups (multi-filter plans); without them the second pass uses q
+  // slices per high digit and the apply one workgroup per chunk
+  const struct PartWork* work2;
+  uint32_t nwork2;
+  const struct PartWork* work3;
+  uint32_t nwork3;
 };
+
+// One unit of work: slice `split` of `nsplit` of bucket `bucket`.
+struct PartWork {
+  uint32_t bucket;
+  uint16_t split;
+  uint16_t nsplit;
+};
+
+__device__ __forceinline__ uint64_t bucket1_base(const PartArgs& a, uint32_t d) {
+  return a.off1 ? a.off1[d] : static_cast<uint64_t>(d) * a.cap1;
+}
+__device__ __forceinline__ uint64_t bucket1_cap(const PartArgs& a, uint32_t d) {
+  return a.off1 ? a.off1[d + 1] - a.off1[d] : a.cap1;
+}
+__device__ __forceinline__ uint64_t bucket2_base(const PartArgs& a, uint64_t c) {
+  return a.off2 ? a.off2[c] : c * a.cap2;
+}
+__device__ __forceinline__ uint64_t bucket2_cap(const PartArgs& a, uint64_t c) {
+  return a.off2 ? a.off2[c + 1] - a.off2[c] : a.cap2;
+}
 
 __device__ __forceinline__ uint32_t rec_block(uint64_t r) { return static_cast<uint32_t>(r >> 32); }
 __device__ __forceinline__ uint32_t rec_lo(uint64_t r) { return static_cast<uint32_t>(r); }
+
+// Words and local block of a record's global block (direct fallback).
+template <typename W>
+__device__ __forceinline__ W* record_target(const PartArgs& a, uint32_t gblock, uint32_t& local) {
+  if (a.nfilters == 1) {
+    local = gblock;
+    return static_cast<W*>(a.words);
+  }
+  const PartFilter& f = a.filters[a.chunk_owner[gblock >> a.chunk_shift]];
+  local = static_cast<uint32_t>(gblock - f.block_base);
+  return static_cast<W*>(f.words);
+}
 
 // One LDS-staged scatter step: the valid records r[] (positions p = tid +
 // j * kPartThreads < valid) with digits dg[] are grouped by digit and
 // written, per digit d, to bucket bucket_of(d) at a reserved offset.
 // Records that do not fit their bucket go to `overflow`.
-template <typename DigitOf, typename BucketOf, typename Overflow>
+template <typename DigitOf, typename BucketOf, typename BaseOf, typename CapOf, typename Overflow>
 __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], const uint32_t (&dg)[kPartPer],
                                              uint32_t valid, uint32_t ndigits, uint64_t* stage,
                                              uint32_t* cnt, uint32_t* start, uint64_t* base,
-                                             unsigned long long* fill, uint64_t cap, uint64_t* buf,
-                                             DigitOf digit_of, BucketOf bucket_of, Overflow overflow) {
+                                             unsigned long long* fill, uint64_t* buf,
+                                             DigitOf digit_of, BucketOf bucket_of, BaseOf base_of,
+                                             CapOf cap_of, Overflow overflow) {
   uint32_t rank[kPartPer];
 #pragma unroll
   for (int j = 0; j < kPartPer; ++j) {
@@ -118,8 +184,8 @@ __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], cons
     const uint64_t v = stage[p];
     const uint32_t d = digit_of(v);
     const uint64_t pos = base[d] + (p - start[d]);
-    if (pos < cap)
-      buf[static_cast<uint64_t>(bucket_of(d)) * cap + pos] = v;
+    if (pos < cap_of(d))
+      buf[base_of(d) + pos] = v;
     else
       overflow(v);
   }
@@ -138,10 +204,23 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a)
   for (uint32_t d = threadIdx.x; d < a.f1; d += kPartThreads) cnt[d] = 0;
   __syncthreads();
   const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
-  W* words = static_cast<W*>(a.words);
   const uint32_t shift = a.chunk_shift + a.low_bits;
   const uint64_t begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
   const uint64_t end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
+  // multi-filter: each thread walks a cursor over the filters (its key
+  // positions only increase) and keeps the current filter's fields in
+  // registers
+  uint32_t cur = a.nfilters > 1 ? a.wg_first[blockIdx.x] : 0;
+  uint64_t cur_end = ~0ull, cur_hinit = a.hash_init, cur_base = 0;
+  uint32_t cur_lo = a.nb_lo, cur_hi = a.nb_hi_mask;
+  if (a.nfilters > 1) {
+    const PartFilter& f = a.filters[cur];
+    cur_end = f.key_end;
+    cur_hinit = f.hash_init;
+    cur_lo = f.nb_lo;
+    cur_hi = f.nb_hi_mask;
+    cur_base = f.block_base;
+  }
   for (uint64_t s = begin; s < end; s += kPartStep) {
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
     uint64_t key[kPartPer];
@@ -154,16 +233,29 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a)
     uint32_t dg[kPartPer];
 #pragma unroll
     for (int j = 0; j < kPartPer; ++j) {
-      const uint64_t h = xxh64_u64(key[j], a.hash_init);
-      const uint32_t blk = block_of(h, a.nb_lo, a.nb_hi_mask);
+      const uint64_t i = s + threadIdx.x + j * kPartThreads;
+      if (i >= cur_end) {  // moved past the current filter's keys
+        while (cur + 1 < a.nfilters && a.filters[cur].key_end <= i) ++cur;
+        const PartFilter& f = a.filters[cur];
+        cur_end = cur + 1 < a.nfilters ? f.key_end : ~0ull;
+        cur_hinit = f.hash_init;
+        cur_lo = f.nb_lo;
+        cur_hi = f.nb_hi_mask;
+        cur_base = f.block_base;
+      }
+      const uint64_t h = xxh64_u64(key[j], cur_hinit);
+      const uint32_t blk = static_cast<uint32_t>(cur_base + block_of(h, cur_lo, cur_hi));
       r[j] = (static_cast<uint64_t>(blk) << 32) | static_cast<uint32_t>(h);
       dg[j] = blk >> shift;
     }
     scatter_step(
-        r, dg, valid, a.f1, stage, cnt, start, base, a.fill1, a.cap1, a.buf1,
+        r, dg, valid, a.f1, stage, cnt, start, base, a.fill1, a.buf1,
         [shift](uint64_t v) { return rec_block(v) >> shift; }, [](uint32_t d) { return d; },
+        [&a](uint32_t d) { return bucket1_base(a, d); }, [&a](uint32_t d) { return bucket1_cap(a, d); },
         [&](uint64_t v) {
-          add_block<W, S_WORDS, K, 1, S_WORDS, false>(words, rec_block(v), rec_lo(v), lp, a.k);
+          uint32_t local;
+          W* w = record_target<W>(a, rec_block(v), local);
+          add_block<W, S_WORDS, K, 1, S_WORDS, false>(w, local, rec_lo(v), lp, a.k);
         });
   }
 }
@@ -179,11 +271,22 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter2_kernel(PartArgs a)
   for (uint32_t d = threadIdx.x; d < a.f2; d += kPartThreads) cnt[d] = 0;
   __syncthreads();
   const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
-  W* words = static_cast<W*>(a.words);
-  const uint32_t d1 = blockIdx.x / a.q, qi = blockIdx.x % a.q;
-  const uint64_t filled = a.fill1[d1] < a.cap1 ? a.fill1[d1] : a.cap1;
-  const uint64_t begin = filled * qi / a.q, end = filled * (qi + 1) / a.q;
-  const uint64_t* src = a.buf1 + static_cast<uint64_t>(d1) * a.cap1;
+  uint32_t d1, qi, nq;
+  if (a.work2) {
+    if (blockIdx.x >= a.nwork2) return;
+    const PartWork w = a.work2[blockIdx.x];
+    d1 = w.bucket;
+    qi = w.split;
+    nq = w.nsplit;
+  } else {
+    d1 = blockIdx.x / a.q;
+    qi = blockIdx.x % a.q;
+    nq = a.q;
+  }
+  const uint64_t cap = bucket1_cap(a, d1);
+  const uint64_t filled = a.fill1[d1] < cap ? a.fill1[d1] : cap;
+  const uint64_t begin = filled * qi / nq, end = filled * (qi + 1) / nq;
+  const uint64_t* src = a.buf1 + bucket1_base(a, d1);
   const uint32_t cshift = a.chunk_shift, mask = a.f2 - 1, f2 = a.f2;
   for (uint64_t s = begin; s < end; s += kPartStep) {
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
@@ -196,11 +299,15 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter2_kernel(PartArgs a)
       dg[j] = (rec_block(r[j]) >> cshift) & mask;
     }
     scatter_step(
-        r, dg, valid, f2, stage, cnt, start, base, a.fill2, a.cap2, a.buf2,
+        r, dg, valid, f2, stage, cnt, start, base, a.fill2, a.buf2,
         [cshift, mask](uint64_t v) { return (rec_block(v) >> cshift) & mask; },
         [d1, f2](uint32_t d) { return d1 * f2 + d; },
+        [&a, d1, f2](uint32_t d) { return bucket2_base(a, static_cast<uint64_t>(d1) * f2 + d); },
+        [&a, d1, f2](uint32_t d) { return bucket2_cap(a, static_cast<uint64_t>(d1) * f2 + d); },
         [&](uint64_t v) {
-          add_block<W, S_WORDS, K, 1, S_WORDS, false>(words, rec_block(v), rec_lo(v), lp, a.k);
+          uint32_t local;
+          W* w = record_target<W>(a, rec_block(v), local);
+          add_block<W, S_WORDS, K, 1, S_WORDS, false>(w, local, rec_lo(v), lp, a.k);
         });
   }
 }
@@ -220,32 +327,55 @@ __global__ __launch_bounds__(kApplyThreads) void part_apply_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t lds_raw[kChunkBytes / 4];
   W* lds = reinterpret_cast<W*>(lds_raw);
   u32x4* lvec = reinterpret_cast<u32x4*>(lds_raw);
-  W* words = static_cast<W*>(a.words);
   const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
   const uint32_t blocks_per_chunk = 1u << a.chunk_shift;
   const uint32_t local_mask = blocks_per_chunk - 1;
   constexpr int kU = 4;
-  for (uint64_t c = blockIdx.x; c < a.chunks; c += gridDim.x) {
-    const uint64_t count = a.fill2[c] < a.cap2 ? a.fill2[c] : a.cap2;
-    if (count == 0) continue;  // untouched chunk: no traffic at all
-    const uint64_t* recs = a.buf2 + c * a.cap2;
-    const uint64_t first_block = c << a.chunk_shift;
-    const uint64_t nblk = a.num_blocks - first_block < blocks_per_chunk ? a.num_blocks - first_block
-                                                                        : blocks_per_chunk;
+  const uint64_t nitems = a.work3 ? a.nwork3 : a.chunks;
+  for (uint64_t item = blockIdx.x; item < nitems; item += gridDim.x) {
+    uint64_t c = item;
+    uint32_t si = 0, ns = 1;
+    if (a.work3) {
+      const PartWork w = a.work3[item];
+      c = w.bucket;
+      si = w.split;
+      ns = w.nsplit;
+    }
+    const uint64_t cap = bucket2_cap(a, c);
+    const uint64_t filled = a.fill2[c] < cap ? a.fill2[c] : cap;
+    const uint64_t rbegin = filled * si / ns;
+    const uint64_t count = filled * (si + 1) / ns - rbegin;
+    if (count == 0) continue;  // untouched: no traffic at all
+    const uint64_t* recs = a.buf2 + bucket2_base(a, c) + rbegin;
+    W* words = static_cast<W*>(a.words);
+    uint64_t num_blocks = a.num_blocks, local_chunk = c;
+    if (a.nfilters > 1) {
+      const PartFilter& f = a.filters[a.chunk_owner[c]];
+      words = static_cast<W*>(f.words);
+      num_blocks = f.num_blocks;
+      local_chunk = c - f.chunk_base;
+    }
+    const uint64_t first_block = local_chunk << a.chunk_shift;
+    const uint64_t nblk = num_blocks - first_block < blocks_per_chunk ? num_blocks - first_block
+                                                                      : blocks_per_chunk;
     const uint32_t nbytes = static_cast<uint32_t>(nblk * S_WORDS * sizeof(W));
     const uint32_t nvec = nbytes / 16;
     const u32x4* gsrc = reinterpret_cast<const u32x4*>(words + first_block * S_WORDS);
-    for (uint32_t i = threadIdx.x; i < nvec; i += kU * kApplyThreads) {
-      u32x4 v[kU];
+    if (ns == 1) {  // sole owner of the chunk: start from its words
+      for (uint32_t i = threadIdx.x; i < nvec; i += kU * kApplyThreads) {
+        u32x4 v[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (i + u * kApplyThreads < nvec) v[u] = gsrc[i + u * kApplyThreads];
+        for (int u = 0; u < kU; ++u)
+          if (i + u * kApplyThreads < nvec) v[u] = gsrc[i + u * kApplyThreads];
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (i + u * kApplyThreads < nvec) lvec[i + u * kApplyThreads] = v[u];
+        for (int u = 0; u < kU; ++u)
+          if (i + u * kApplyThreads < nvec) lvec[i + u * kApplyThreads] = v[u];
+      }
+      for (uint32_t i = nvec * 4 + threadIdx.x; i < nbytes / 4; i += kApplyThreads)
+        lds_raw[i] = reinterpret_cast<const uint32_t*>(gsrc)[i];
+    } else {  // one of several: accumulate this slice's bits only
+      for (uint32_t i = threadIdx.x; i < nbytes / 4; i += kApplyThreads) lds_raw[i] = 0u;
     }
-    for (uint32_t i = nvec * 4 + threadIdx.x; i < nbytes / 4; i += kApplyThreads)
-      lds_raw[i] = reinterpret_cast<const uint32_t*>(gsrc)[i];
     __syncthreads();
     for (uint64_t i = threadIdx.x; i < count; i += kU * kApplyThreads) {
       uint64_t r[kU];
@@ -269,9 +399,16 @@ __global__ __launch_bounds__(kApplyThreads) void part_apply_kernel(PartArgs a) {
     }
     __syncthreads();
     u32x4* gdst = reinterpret_cast<u32x4*>(words + first_block * S_WORDS);
-    for (uint32_t i = threadIdx.x; i < nvec; i += kApplyThreads) gdst[i] = lvec[i];
-    for (uint32_t i = nvec * 4 + threadIdx.x; i < nbytes / 4; i += kApplyThreads)
-      reinterpret_cast<uint32_t*>(gdst)[i] = lds_raw[i];
+    if (ns == 1) {
+      for (uint32_t i = threadIdx.x; i < nvec; i += kApplyThreads) gdst[i] = lvec[i];
+      for (uint32_t i = nvec * 4 + threadIdx.x; i < nbytes / 4; i += kApplyThreads)
+        reinterpret_cast<uint32_t*>(gdst)[i] = lds_raw[i];
+    } else {  // slices of one chunk merge with atomic OR of the words they set
+      uint32_t* g32 = reinterpret_cast<uint32_t*>(gdst);
+      for (uint32_t i = threadIdx.x; i < nbytes / 4; i += kApplyThreads)
+        if (lds_raw[i]) __hip_atomic_fetch_or(g32 + i, lds_raw[i], __ATOMIC_RELAXED,
+                                              __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
   }
 }

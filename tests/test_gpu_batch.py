@@ -51,9 +51,11 @@ def _oracle(params, offsets, keys, queries):
     return words, outs
 
 
-def _run(params, offsets, keys, queries, mode):
+def _run(params, offsets, keys, queries, mode, add_strategy=None):
     bf = _bf()
     filters = [bf.BloomFilter(**p) for p in params]
+    if add_strategy is not None:
+        filters[0].set_mapping(bf.BF_OP_ADD, strategy=add_strategy)
     d_keys = torch.from_numpy(keys.view(np.int64)).to("cuda")
     d_q = torch.from_numpy(queries.view(np.int64)).to("cuda")
     d_out = torch.full((queries.size,), 7, dtype=torch.uint8, device="cuda")
@@ -137,3 +139,28 @@ def test_batch_replay_and_empty_filters():
         con.close()
         for f in filters:
             f.close()
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct"])
+def test_batch_partitioned_add(mode):
+    """One partitioned construction over all filters of a plan (forced):
+    skewed key counts, empty filters, a filter of repeated keys (its chunk
+    buckets overflow into the direct fallback), filters of every size class."""
+    bf = _bf()
+    params, offsets, keys, queries = _make_batch(200, 1 << 19, sizes_extra=(8 << 20, 300 << 20), seed=61)
+    counts = np.diff(offsets)
+    counts[5] = 0
+    counts[17] = 0
+    offsets = np.concatenate([[0], np.cumsum(counts)])
+    keys = keys[: offsets[-1]].copy()
+    queries = queries[: offsets[-1]]
+    i = int(np.argmax(counts))                   # the busiest filter gets repeats
+    keys[offsets[i]: offsets[i] + counts[i] // 2] = keys[offsets[i]]
+    log(f"batch partitioned mode={mode}: {len(params)} filters, {keys.size} keys")
+    want_words, want_out = _oracle(params, offsets, keys, queries)
+    words, out, (ia, ic) = _run(params, offsets, keys, queries, mode,
+                                add_strategy=bf.BF_STRATEGY_PARTITIONED)
+    assert ia.strategy == bf.BF_STRATEGY_PARTITIONED
+    for j in range(len(params)):
+        assert np.array_equal(words[j], want_words[j]), f"filter {j}"
+    assert np.array_equal(out, want_out)

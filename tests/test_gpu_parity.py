@@ -242,3 +242,24 @@ def test_auto_strategy_matches_direct():
     want = oracle.block_words(params["num_blocks"], 8, 32, 8, 3, adds, sel)
     rows = words[0].reshape(params["num_blocks"], -1)[sel.astype(np.int64)]
     assert np.array_equal(rows, want)
+
+
+def test_partitioned_overflow_with_repeated_keys():
+    """Repeated keys pile into one chunk beyond its bucket capacity; the
+    overflowing records take the direct-atomic fallback and the words still
+    equal the oracle's."""
+    bf = _bf()
+    params = dict(num_blocks=(4 << 20) // 32, words_per_block=8, word_bits=32, k=8, seed=11)
+    g = workloads.rng(99)
+    few = g.integers(0, 2**64, size=3, dtype=np.uint64)
+    adds = np.concatenate([np.repeat(few, 200_000), g.integers(0, 2**64, size=100_000, dtype=np.uint64)])
+    adds = adds[g.permutation(adds.size)]
+    want_words, _ = _oracle(params, adds, adds[:1])
+    f = bf.BloomFilter(**params)
+    try:
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        f.add(to_device(adds))
+        assert np.array_equal(f.words().cpu().numpy(), want_words)
+        torch.cuda.synchronize()
+    finally:
+        f.close()
