@@ -8,7 +8,8 @@ ctypes and shares nothing with the HIP library.
 The filter definition follows "Optimizing Bloom Filters on Modern GPUs"
 (arXiv 2512.15595): Sec. II-A-2/3/4 for the blocked, register-blocked and
 sectorized layouts, Sec. IV-B for one xxHash64 base hash per key and salted
-multiplicative bit positions.  ``bf_oracle.h`` lists the readings taken where
+multiplicative bit positions; Sec. II-A-1 for the classic (unblocked) filter
+and Sec. II-A-5 with Sec. V-A for the cache-sectorized filter.  ``bf_oracle.h`` lists the readings taken where
 the paper is silent.
 """
 from __future__ import annotations
@@ -70,6 +71,27 @@ def _load():
         lib.oracle_clear.restype = None
         lib.oracle_block_words.argtypes = [u64, u32, u32, u32, u64, vp, u64, vp, u64, vp]
         lib.oracle_block_words.restype = i32
+        lib.oracle_salts64.argtypes = [vp]
+        lib.oracle_salts64.restype = None
+        lib.oracle_classic_position.argtypes = [u64, u64, u32]
+        lib.oracle_classic_position.restype = u64
+        lib.oracle_classic_add.argtypes = [vp, u64, u32, u64, vp, u64]
+        lib.oracle_classic_add.restype = i32
+        lib.oracle_classic_contains.argtypes = [vp, u64, u32, u64, vp, u64, vp]
+        lib.oracle_classic_contains.restype = i32
+        lib.oracle_classic_words.argtypes = [u64, u32, u64, vp, u64, vp, u64, vp]
+        lib.oracle_classic_words.restype = i32
+        lib.oracle_check_csbf_params.argtypes = [u64, u32, u32, u32, u32]
+        lib.oracle_check_csbf_params.restype = i32
+        lib.oracle_group_salts.argtypes = [vp]
+        lib.oracle_group_salts.restype = None
+        lib.oracle_csbf_add.argtypes = [vp, u64, u32, u32, u32, u32, u64, vp, u64]
+        lib.oracle_csbf_add.restype = i32
+        lib.oracle_csbf_contains.argtypes = [vp, u64, u32, u32, u32, u32, u64, vp, u64, vp]
+        lib.oracle_csbf_contains.restype = i32
+        lib.oracle_csbf_block_words.argtypes = [u64, u32, u32, u32, u32, u64, vp, u64, vp,
+                                                u64, vp]
+        lib.oracle_csbf_block_words.restype = i32
         _lib = lib
     return _lib
 
@@ -165,6 +187,130 @@ def block_words(num_blocks: int, words_per_block: int, word_bits: int, k: int,
     rc = _load().oracle_block_words(num_blocks, words_per_block, word_bits, k,
                                     seed & (2**64 - 1), _ptr(keys), keys.size,
                                     _ptr(sel), sel.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad parameters or block selection")
+    return out[: sel.size]
+
+
+def salts64() -> list[int]:
+    out = np.zeros(MAX_K, dtype=np.uint64)
+    _load().oracle_salts64(_ptr(out))
+    return [int(v) for v in out]
+
+
+def group_salts() -> list[int]:
+    out = np.zeros(16, dtype=np.uint32)
+    _load().oracle_group_salts(_ptr(out))
+    return [int(v) for v in out]
+
+
+def classic_position(h: int, num_bits: int, j: int) -> int:
+    return int(_load().oracle_classic_position(h & (2**64 - 1), num_bits, j))
+
+
+def check_classic_params(num_bits: int, k: int) -> bool:
+    return num_bits >= 64 and num_bits % 64 == 0 and 1 <= k <= MAX_K
+
+
+def check_csbf_params(num_blocks: int, words_per_block: int, word_bits: int,
+                      groups: int, k: int) -> bool:
+    if not (0 <= num_blocks < 2**64):
+        return False
+    return _load().oracle_check_csbf_params(num_blocks, words_per_block, word_bits,
+                                            groups, k) == 0
+
+
+class ClassicOracle:
+    """Classic filter of ``num_bits`` bits (Sec. II-A-1) in host memory."""
+
+    def __init__(self, num_bits: int, k: int, seed: int = 0):
+        if not check_classic_params(num_bits, k):
+            raise ValueError("bad filter parameters")
+        self.num_bits, self.k, self.seed = num_bits, k, seed & (2**64 - 1)
+        self.nbytes = num_bits // 8
+        self.bytes = np.zeros(self.nbytes, dtype=np.uint8)
+
+    def add(self, keys) -> None:
+        keys = _keys(keys)
+        rc = _load().oracle_classic_add(_ptr(self.bytes), self.num_bits, self.k, self.seed,
+                                        _ptr(keys), keys.size)
+        assert rc == 0
+
+    def contains(self, keys) -> np.ndarray:
+        keys = _keys(keys)
+        out = np.zeros(max(keys.size, 1), dtype=np.uint8)
+        rc = _load().oracle_classic_contains(_ptr(self.bytes), self.num_bits, self.k,
+                                             self.seed, _ptr(keys), keys.size, _ptr(out))
+        assert rc == 0
+        return out[: keys.size]
+
+    def clear(self) -> None:
+        _load().oracle_clear(_ptr(self.bytes), self.nbytes)
+
+
+def classic_words(num_bits: int, k: int, seed: int, keys, words) -> np.ndarray:
+    """Selected 64-bit words of a classic filter after adding ``keys``."""
+    keys = _keys(keys)
+    sel = np.ascontiguousarray(np.asarray(words, dtype=np.uint64))
+    out = np.zeros(max(sel.size, 1), dtype=np.uint64)
+    rc = _load().oracle_classic_words(num_bits, k, seed & (2**64 - 1), _ptr(keys), keys.size,
+                                      _ptr(sel), sel.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad parameters or word selection")
+    return out[: sel.size]
+
+
+class CsbfOracle:
+    """Cache-sectorized filter (Sec. II-A-5) in host memory."""
+
+    def __init__(self, num_blocks: int, words_per_block: int, word_bits: int,
+                 groups: int, k: int, seed: int = 0):
+        if not check_csbf_params(num_blocks, words_per_block, word_bits, groups, k):
+            raise ValueError("bad filter parameters")
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.groups = groups
+        self.k = k
+        self.seed = seed & (2**64 - 1)
+        self.nbytes = num_blocks * words_per_block * word_bits // 8
+        self.bytes = np.zeros(self.nbytes, dtype=np.uint8)
+
+    def _args(self):
+        return (self.num_blocks, self.words_per_block, self.word_bits, self.groups, self.k,
+                self.seed)
+
+    def add(self, keys) -> None:
+        keys = _keys(keys)
+        rc = _load().oracle_csbf_add(_ptr(self.bytes), *self._args(), _ptr(keys), keys.size)
+        assert rc == 0
+
+    def contains(self, keys) -> np.ndarray:
+        keys = _keys(keys)
+        out = np.zeros(max(keys.size, 1), dtype=np.uint8)
+        rc = _load().oracle_csbf_contains(_ptr(self.bytes), *self._args(), _ptr(keys),
+                                          keys.size, _ptr(out))
+        assert rc == 0
+        return out[: keys.size]
+
+    def clear(self) -> None:
+        _load().oracle_clear(_ptr(self.bytes), self.nbytes)
+
+    def words(self) -> np.ndarray:
+        dt = np.dtype("<u4") if self.word_bits == 32 else np.dtype("<u8")
+        return self.bytes.view(dt)
+
+
+def csbf_block_words(num_blocks: int, words_per_block: int, word_bits: int, groups: int,
+                     k: int, seed: int, keys, blocks) -> np.ndarray:
+    """Bytes of the selected blocks of a cache-sectorized filter after ``keys``."""
+    keys = _keys(keys)
+    sel = np.ascontiguousarray(np.asarray(blocks, dtype=np.uint64))
+    block_bytes = words_per_block * word_bits // 8
+    out = np.zeros((max(sel.size, 1), block_bytes), dtype=np.uint8)
+    rc = _load().oracle_csbf_block_words(num_blocks, words_per_block, word_bits, groups, k,
+                                         seed & (2**64 - 1), _ptr(keys), keys.size,
+                                         _ptr(sel), sel.size, _ptr(out))
     if rc != 0:
         raise ValueError("bad parameters or block selection")
     return out[: sel.size]

@@ -285,3 +285,211 @@ int oracle_block_words(uint64_t num_blocks, uint32_t words_per_block,
     free(slot_of);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Classic (unblocked) filter, Sec. II-A-1.                                  */
+/* ------------------------------------------------------------------------ */
+
+void oracle_salts64(uint64_t out[ORACLE_MAX_K]) {
+    for (uint32_t j = 0; j < ORACLE_MAX_K; ++j)
+        out[j] = oracle_hash_key((uint64_t)j, ORACLE_SALT_SEED) | 1ULL;
+}
+
+static uint64_t classic_position_with_salt(uint64_t h, uint64_t num_bits, uint64_t salt) {
+    uint64_t product = h * salt;                              /* mod 2^64 */
+    return (uint64_t)(((unsigned __int128)product * num_bits) >> 64);
+}
+
+uint64_t oracle_classic_position(uint64_t h, uint64_t num_bits, uint32_t j) {
+    uint64_t salts[ORACLE_MAX_K];
+    oracle_salts64(salts);
+    return classic_position_with_salt(h, num_bits, salts[j % ORACLE_MAX_K]);
+}
+
+static int classic_ok(uint64_t num_bits, uint32_t k) {
+    return num_bits >= 64 && num_bits % 64 == 0 && k >= 1 && k <= ORACLE_MAX_K;
+}
+
+int oracle_classic_add(uint8_t *filter, uint64_t num_bits, uint32_t k, uint64_t seed,
+                       const uint64_t *keys, uint64_t n) {
+    if (!classic_ok(num_bits, k)) return -1;
+    uint64_t salts[ORACLE_MAX_K];
+    oracle_salts64(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        for (uint32_t j = 0; j < k; ++j) {
+            uint64_t p = classic_position_with_salt(h, num_bits, salts[j]);
+            filter[p / 8] = (uint8_t)(filter[p / 8] | (1u << (p % 8)));
+        }
+    }
+    return 0;
+}
+
+int oracle_classic_contains(const uint8_t *filter, uint64_t num_bits, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n,
+                            uint8_t *out) {
+    if (!classic_ok(num_bits, k)) return -1;
+    uint64_t salts[ORACLE_MAX_K];
+    oracle_salts64(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        int all_set = 1;
+        for (uint32_t j = 0; j < k; ++j) {
+            uint64_t p = classic_position_with_salt(h, num_bits, salts[j]);
+            if (!((filter[p / 8] >> (p % 8)) & 1)) all_set = 0;
+        }
+        out[i] = (uint8_t)all_set;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Cache-sectorized filter, Sec. II-A-5.                                     */
+/* ------------------------------------------------------------------------ */
+
+int oracle_check_csbf_params(uint64_t num_blocks, uint32_t words_per_block,
+                             uint32_t word_bits, uint32_t groups, uint32_t k) {
+    uint32_t s = words_per_block, z = groups;
+    if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return -1;
+    if (!(word_bits == 32 || word_bits == 64)) return -1;
+    if (!(z == 1 || z == 2 || z == 4 || z == 8 || z == 16) || z > s) return -1;
+    if (k < z || k > ORACLE_MAX_K || k % z != 0) return -1;
+    if (num_blocks < 1 || num_blocks > (1ULL << 32)) return -1;
+    return 0;
+}
+
+void oracle_group_salts(uint32_t out[16]) {
+    for (uint32_t g = 0; g < 16; ++g) {
+        uint64_t h = oracle_hash_key((uint64_t)(32 + g), ORACLE_SALT_SEED);
+        out[g] = (uint32_t)(h & 0xFFFFFFFFULL) | 1u;
+    }
+}
+
+static unsigned log2u(uint32_t v) {
+    unsigned r = 0;
+    while ((1u << r) < v) ++r;
+    return r;
+}
+
+/* Word index (within the block) of group g for hash low word lo. */
+static uint32_t csbf_word(uint32_t lo, uint32_t s, uint32_t z, uint32_t g,
+                          const uint32_t *gsalts) {
+    uint32_t width = s / z;                 /* words per group */
+    uint32_t sel = 0;
+    if (width > 1) sel = (lo * gsalts[g]) >> (32u - log2u(width));
+    return g * width + sel;
+}
+
+/* Apply (do_set) or test one key's bits in the block whose first word is
+ * first_word.  Group g = j mod z receives bit j in its selected word. */
+static int csbf_touch(uint8_t *filter, uint64_t first_word, uint64_t h, uint32_t s,
+                      uint32_t S, uint32_t z, uint32_t k, const uint32_t *salts,
+                      const uint32_t *gsalts, int do_set) {
+    uint32_t lo = (uint32_t)(h & 0xFFFFFFFFULL);
+    unsigned L = log2_word_bits(S);
+    int all_set = 1;
+    for (uint32_t j = 0; j < k; ++j) {
+        uint32_t g = j % z;
+        uint32_t w = csbf_word(lo, s, z, g, gsalts);
+        unsigned p = (lo * salts[j]) >> (32u - L);
+        if (do_set)
+            set_bit(filter, first_word + w, S, p);
+        else if (!get_bit(filter, first_word + w, S, p))
+            all_set = 0;
+    }
+    return all_set;
+}
+
+int oracle_csbf_add(uint8_t *filter, uint64_t num_blocks, uint32_t words_per_block,
+                    uint32_t word_bits, uint32_t groups, uint32_t k, uint64_t seed,
+                    const uint64_t *keys, uint64_t n) {
+    if (oracle_check_csbf_params(num_blocks, words_per_block, word_bits, groups, k) != 0)
+        return -1;
+    uint32_t salts[ORACLE_MAX_K], gsalts[16];
+    oracle_salts(salts);
+    oracle_group_salts(gsalts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint64_t blk = oracle_block_index(h, num_blocks);
+        csbf_touch(filter, blk * words_per_block, h, words_per_block, word_bits, groups,
+                   k, salts, gsalts, 1);
+    }
+    return 0;
+}
+
+int oracle_csbf_contains(const uint8_t *filter, uint64_t num_blocks,
+                         uint32_t words_per_block, uint32_t word_bits, uint32_t groups,
+                         uint32_t k, uint64_t seed, const uint64_t *keys, uint64_t n,
+                         uint8_t *out) {
+    if (oracle_check_csbf_params(num_blocks, words_per_block, word_bits, groups, k) != 0)
+        return -1;
+    uint32_t salts[ORACLE_MAX_K], gsalts[16];
+    oracle_salts(salts);
+    oracle_group_salts(gsalts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint64_t blk = oracle_block_index(h, num_blocks);
+        out[i] = (uint8_t)csbf_touch((uint8_t *)filter, blk * words_per_block, h,
+                                     words_per_block, word_bits, groups, k, salts, gsalts, 0);
+    }
+    return 0;
+}
+
+/* Selected 64-bit words of a classic filter, computed from the keys alone:
+ * out[i] = word sel[i] (bits sel[i]*64 .. +63, little-endian) after adding
+ * keys[0..n).  sel holds distinct word indices < num_bits / 64. */
+int oracle_classic_words(uint64_t num_bits, uint32_t k, uint64_t seed,
+                         const uint64_t *keys, uint64_t n, const uint64_t *sel,
+                         uint64_t nsel, uint64_t *out) {
+    if (!classic_ok(num_bits, k)) return -1;
+    uint64_t nwords = num_bits / 64;
+    uint32_t *slot_of = (uint32_t *)calloc(nwords, sizeof(uint32_t));
+    if (!slot_of) return -1;
+    for (uint64_t i = 0; i < nsel; ++i) {
+        if (sel[i] >= nwords || slot_of[sel[i]] != 0) { free(slot_of); return -1; }
+        slot_of[sel[i]] = (uint32_t)(i + 1);
+        out[i] = 0;
+    }
+    uint64_t salts[ORACLE_MAX_K];
+    oracle_salts64(salts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        for (uint32_t j = 0; j < k; ++j) {
+            uint64_t p = classic_position_with_salt(h, num_bits, salts[j]);
+            uint32_t slot = slot_of[p / 64];
+            if (slot) out[slot - 1] |= 1ULL << (p % 64);
+        }
+    }
+    free(slot_of);
+    return 0;
+}
+
+/* Selected blocks of a cache-sectorized filter (as oracle_block_words). */
+int oracle_csbf_block_words(uint64_t num_blocks, uint32_t words_per_block,
+                            uint32_t word_bits, uint32_t groups, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n,
+                            const uint64_t *sel, uint64_t nsel, uint8_t *out) {
+    if (oracle_check_csbf_params(num_blocks, words_per_block, word_bits, groups, k) != 0)
+        return -1;
+    uint32_t *slot_of = (uint32_t *)calloc(num_blocks, sizeof(uint32_t));
+    if (!slot_of) return -1;
+    for (uint64_t i = 0; i < nsel; ++i) {
+        if (sel[i] >= num_blocks || slot_of[sel[i]] != 0) { free(slot_of); return -1; }
+        slot_of[sel[i]] = (uint32_t)(i + 1);
+    }
+    uint64_t block_bytes = (uint64_t)words_per_block * word_bits / 8;
+    memset(out, 0, nsel * block_bytes);
+    uint32_t salts[ORACLE_MAX_K], gsalts[16];
+    oracle_salts(salts);
+    oracle_group_salts(gsalts);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t h = oracle_hash_key(keys[i], seed);
+        uint32_t slot = slot_of[oracle_block_index(h, num_blocks)];
+        if (!slot) continue;
+        /* The add rule, applied to the copy of the selected block. */
+        csbf_touch(out, (uint64_t)(slot - 1) * words_per_block, h, words_per_block,
+                   word_bits, groups, k, salts, gsalts, 1);
+    }
+    free(slot_of);
+    return 0;
+}

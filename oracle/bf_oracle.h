@@ -86,6 +86,52 @@ int oracle_block_words(uint64_t num_blocks, uint32_t words_per_block,
                        const uint64_t *keys, uint64_t n, const uint64_t *sel,
                        uint64_t nsel, uint8_t *out);
 
+/* ------------------------------------------------------------------------
+ * Classic (unblocked) Bloom filter, Sec. II-A-1: m bits, k positions
+ * anywhere.  Readings: position j of a key is floor(((h * A_j) mod 2^64) *
+ * m / 2^64) with the 64-bit odd salts A_j = XXH64(LE64(j), SALT_SEED) | 1
+ * (whose low halves are the 32-bit salts a_j); bit p lives at byte p / 8,
+ * bit p % 8.  m is a multiple of 64; 1 <= k <= 32.
+ * ------------------------------------------------------------------------ */
+void oracle_salts64(uint64_t out[ORACLE_MAX_K]);
+uint64_t oracle_classic_position(uint64_t h, uint64_t num_bits, uint32_t j);
+int oracle_classic_add(uint8_t *filter, uint64_t num_bits, uint32_t k, uint64_t seed,
+                       const uint64_t *keys, uint64_t n);
+int oracle_classic_contains(const uint8_t *filter, uint64_t num_bits, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n,
+                            uint8_t *out);
+/* Selected 64-bit words (indices sel[0..nsel), distinct) after adding keys. */
+int oracle_classic_words(uint64_t num_bits, uint32_t k, uint64_t seed,
+                         const uint64_t *keys, uint64_t n, const uint64_t *sel,
+                         uint64_t nsel, uint64_t *out);
+
+/* ------------------------------------------------------------------------
+ * Cache-sectorized Bloom filter, Sec. II-A-5: the s words of a block form z
+ * groups of s/z consecutive words; a key selects one word per group and
+ * puts its bits j with j mod z == g into group g's selected word.
+ * Readings: the word selected in group g is the top log2(s/z) bits of
+ * (lo32(h) * c_g mod 2^32), with a further odd multiplier per group
+ * c_g = (XXH64(LE64(32 + g), SALT_SEED) mod 2^32) | 1; bit positions are
+ * those of the sectorized filter.  z is a power of two, 1 <= z <= s,
+ * z <= k <= 32, k a multiple of z (each selected word receives k/z bits).
+ * With z = s this is exactly the sectorized filter.
+ * ------------------------------------------------------------------------ */
+int oracle_check_csbf_params(uint64_t num_blocks, uint32_t words_per_block,
+                             uint32_t word_bits, uint32_t groups, uint32_t k);
+void oracle_group_salts(uint32_t out[16]);
+int oracle_csbf_add(uint8_t *filter, uint64_t num_blocks, uint32_t words_per_block,
+                    uint32_t word_bits, uint32_t groups, uint32_t k, uint64_t seed,
+                    const uint64_t *keys, uint64_t n);
+int oracle_csbf_contains(const uint8_t *filter, uint64_t num_blocks,
+                         uint32_t words_per_block, uint32_t word_bits, uint32_t groups,
+                         uint32_t k, uint64_t seed, const uint64_t *keys, uint64_t n,
+                         uint8_t *out);
+/* Selected blocks after adding keys, as oracle_block_words. */
+int oracle_csbf_block_words(uint64_t num_blocks, uint32_t words_per_block,
+                            uint32_t word_bits, uint32_t groups, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n,
+                            const uint64_t *sel, uint64_t nsel, uint8_t *out);
+
 #ifdef __cplusplus
 }
 #endif

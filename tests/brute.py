@@ -63,3 +63,68 @@ def triples_of_bytes(filter_bytes, s: int, S: int) -> set:
                 p = (byte_index % wbytes) * 8 + bit
                 out.add((word_index // s, word_index % s, p))
     return out
+
+
+# -- classic filter (Sec. II-A-1): positions anywhere in m bits -------------
+
+def salts64() -> list[int]:
+    return [base_hash(j, SALT_SEED) | 1 for j in range(32)]
+
+
+_SALTS64 = salts64()
+
+
+def classic_positions(key: int, m: int, k: int, seed: int) -> set:
+    h = base_hash(key, seed)
+    return {(((h * _SALTS64[j]) & M64) * m) >> 64 for j in range(k)}
+
+
+def classic_build(keys, m: int, k: int, seed: int) -> set:
+    bits = set()
+    for x in keys:
+        bits |= classic_positions(int(x), m, k, seed)
+    return bits
+
+
+def positions_of_bytes(filter_bytes) -> set:
+    """Bit p is bit p % 8 of byte p // 8."""
+    out = set()
+    for byte_index, value in enumerate(bytes(filter_bytes)):
+        for bit in range(8):
+            if (value >> bit) & 1:
+                out.add(byte_index * 8 + bit)
+    return out
+
+
+# -- cache-sectorized filter (Sec. II-A-5): one word per group --------------
+
+def group_salts() -> list[int]:
+    return [(base_hash(32 + g, SALT_SEED) & M32) | 1 for g in range(16)]
+
+
+_GSALTS = group_salts()
+
+
+def csbf_triples_of_key(key: int, b: int, s: int, S: int, z: int, k: int, seed: int) -> set:
+    h = base_hash(key, seed)
+    hi, lo = h >> 32, h & M32
+    blk = hi * b // 2**32
+    L = S.bit_length() - 1
+    width = s // z
+    wl = width.bit_length() - 1
+    chosen = []
+    for g in range(z):
+        sel = (((lo * _GSALTS[g]) & M32) >> (32 - wl)) if wl else 0
+        chosen.append(g * width + sel)
+    out = set()
+    for j in range(k):
+        p = ((lo * _SALTS[j]) & M32) >> (32 - L)
+        out.add((blk, chosen[j % z], p))
+    return out
+
+
+def csbf_build(keys, b: int, s: int, S: int, z: int, k: int, seed: int) -> set:
+    bits = set()
+    for x in keys:
+        bits |= csbf_triples_of_key(int(x), b, s, S, z, k, seed)
+    return bits

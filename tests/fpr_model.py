@@ -16,6 +16,12 @@ that every pattern bit is an independent uniform position in its word:
   equivalent, cancellation-free Markov chain over the number covered;
 * words are independent given l, so FPR = sum_l P(l) prod_w q_w(l).
 
+The same model covers the classic filter of Sec. II-A-1 (one "word" of m
+bits, n*k throws; ``classic_fpr``) and the cache-sectorized filter of
+Sec. II-A-5 (``csbf_fpr``): within the query's block, each of the z groups
+has one selected word, whose load is Binomial(l, z/s) keys of k/z bits each,
+and the groups are independent given l.
+
 Everything is float64.  This is a model, not an implementation: it pins the
 oracle statistically, independent of how the oracle computes bits.
 """
@@ -114,3 +120,48 @@ def sbf_fill_fraction(n: int, b: int, s: int, S: int, k: int) -> float:
 def cbf_fpr_eq1(c: float, k: int) -> float:
     """Eq. (1) of the paper: classic filter, c bits per key."""
     return (1.0 - math.exp(-k / c)) ** k
+
+
+def cover_prob_float(d: int, m: int, M: int) -> float:
+    """P(d given bins of m are all hit by M uniform throws), inclusion-exclusion
+    in float64 (fine for the moderate cancellation of the cases used here)."""
+    total = 0.0
+    for i in range(d + 1):
+        total += (-1) ** i * math.comb(d, i) * math.exp(M * math.log1p(-i / m))
+    return total
+
+
+def classic_fpr(n: int, m: int, k: int) -> float:
+    """Classic filter of m bits after n distinct keys, k uniform positions each."""
+    dp = distinct_probs(k, m)
+    return float(sum(dp[d] * cover_prob_float(d, m, n * k) for d in range(1, k + 1)))
+
+
+def classic_fill_fraction(n: int, m: int, k: int) -> float:
+    return 1.0 - math.exp(n * k * math.log1p(-1.0 / m))
+
+
+def csbf_fpr(n: int, b: int, s: int, S: int, z: int, k: int) -> float:
+    """Cache-sectorized filter: z groups of s/z words, k/z bits per selected word."""
+    assert k % z == 0 and s % z == 0
+    t, width = k // z, s // z
+    ls, pl = _load_pmf(n, b)
+    lmax = int(ls[-1])
+    dp = distinct_probs(t, S)
+    q = np.zeros(lmax + 1)                    # q[l] for l keys in the query's word
+    for d in range(1, t + 1):
+        if dp[d] == 0.0:
+            continue
+        q += dp[d] * cover_probs(d, S, lmax * t)[np.arange(lmax + 1) * t]
+    per_l = np.empty(ls.size)
+    for i, L in enumerate(ls):
+        w = binom.pmf(np.arange(L + 1), L, 1.0 / width)
+        per_l[i] = float(np.dot(w, q[: L + 1])) ** z
+    return float(np.sum(pl * per_l))
+
+
+def csbf_fill_fraction(n: int, b: int, s: int, S: int, z: int, k: int) -> float:
+    t, width = k // z, s // z
+    ls, pl = _load_pmf(n, b)
+    hit = (1.0 - (1.0 - 1.0 / S) ** t) / width   # one key sets a given bit of a word
+    return float(np.sum(pl * (1.0 - (1.0 - hit) ** ls)))
