@@ -93,16 +93,25 @@ typedef struct {
   uint32_t strategy;
 } bf_mapping_t;
 
+/* Filter layouts (bf_info_t.layout).  bf_create makes the sectorized
+ * layout; bf_variants.h creates the other two. */
+#define BF_LAYOUT_SECTORIZED 0       /* Sec. II-A-4 (s = 1: register-blocked) */
+#define BF_LAYOUT_CLASSIC 1          /* Sec. II-A-1: k positions over m bits */
+#define BF_LAYOUT_CACHE_SECTORIZED 2 /* Sec. II-A-5: one word per group of s/z */
+
 typedef struct {
-  uint64_t num_blocks;
-  uint32_t words_per_block;
-  uint32_t word_bits;
+  uint64_t num_blocks;     /* 0 for the classic layout */
+  uint32_t words_per_block;/* 0 for the classic layout */
+  uint32_t word_bits;      /* 32 for the classic layout (its word array) */
   uint32_t k;
   int32_t device;          /* HIP device the words live on */
   uint64_t seed;
-  uint64_t size_bytes;     /* num_blocks * words_per_block * word_bits / 8 */
+  uint64_t size_bytes;     /* bytes of filter state */
   void *d_words;           /* device address of the words (owned by the filter) */
   bf_mapping_t mapping[2]; /* resolved mapping per op, indexed by BF_OP_* */
+  uint32_t layout;         /* BF_LAYOUT_* */
+  uint32_t groups;         /* z of the cache-sectorized layout, else 0 */
+  uint64_t num_bits;       /* size_bytes * 8 */
 } bf_info_t;
 
 /* Creates a filter on the current HIP device with all words zero.

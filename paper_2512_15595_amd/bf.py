@@ -34,6 +34,9 @@ BF_OP_CONTAINS = 1
 BF_STRATEGY_AUTO = 0
 BF_STRATEGY_DIRECT = 1
 BF_STRATEGY_PARTITIONED = 2
+BF_LAYOUT_SECTORIZED = 0
+BF_LAYOUT_CLASSIC = 1
+BF_LAYOUT_CACHE_SECTORIZED = 2
 
 
 class bf_mapping_t(ctypes.Structure):
@@ -61,12 +64,19 @@ class bf_info_t(ctypes.Structure):
         ("size_bytes", ctypes.c_uint64),
         ("d_words", ctypes.c_void_p),
         ("mapping", bf_mapping_t * 2),
+        ("layout", ctypes.c_uint32),
+        ("groups", ctypes.c_uint32),
+        ("num_bits", ctypes.c_uint64),
     ]
 
 
 _u64, _u32, _i32, _vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p
 _lib.bf_create.argtypes = [_u64, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create.restype = _i32
+_lib.bf_create_classic.argtypes = [_u64, _u32, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create_classic.restype = _i32
+_lib.bf_create_csbf.argtypes = [_u64, _u32, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create_csbf.restype = _i32
 _lib.bf_destroy.argtypes = [_vp]
 _lib.bf_destroy.restype = _i32
 _lib.bf_add.argtypes = [_vp, _vp, _u64, _vp]
@@ -193,6 +203,22 @@ def bf_create(num_blocks: int, words_per_block: int, word_bits: int, k: int, see
     return st, h
 
 
+def bf_create_classic(num_bits: int, k: int, seed: int):
+    """Returns (status, handle)."""
+    h = _vp()
+    st = _lib.bf_create_classic(num_bits, k, seed & (2**64 - 1), ctypes.byref(h))
+    return st, h
+
+
+def bf_create_csbf(num_blocks: int, words_per_block: int, word_bits: int, groups: int, k: int,
+                   seed: int):
+    """Returns (status, handle)."""
+    h = _vp()
+    st = _lib.bf_create_csbf(num_blocks, words_per_block, word_bits, groups, k,
+                             seed & (2**64 - 1), ctypes.byref(h))
+    return st, h
+
+
 def bf_destroy(f) -> int:
     return _lib.bf_destroy(f)
 
@@ -281,19 +307,18 @@ def _stream_ptr(stream) -> int:
     return int(stream.cuda_stream)
 
 
-class BloomFilter:
-    """A device-resident filter; keys and results are torch tensors on the GPU."""
+class _Filter:
+    """Methods shared by every layout; subclasses create the handle."""
 
-    def __init__(self, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
-                 k: int = 8, seed: int = 0):
-        st, h = bf_create(num_blocks, words_per_block, word_bits, k, seed)
-        _check(st, "bf_create")
+    _h = None
+
+    def _adopt(self, st: int, h, what: str) -> None:
+        _check(st, what)
         self._h = h
-        self.num_blocks = num_blocks
-        self.words_per_block = words_per_block
-        self.word_bits = word_bits
-        self.k = k
-        self.seed = seed
+        info = self.info()
+        self.layout = int(info.layout)
+        self.k = int(info.k)
+        self._nbytes = int(info.size_bytes)
 
     @property
     def handle(self):
@@ -364,7 +389,44 @@ class BloomFilter:
                "bf_import_words")
 
     def size_bytes(self) -> int:
-        return self.num_blocks * self.words_per_block * self.word_bits // 8
+        return self._nbytes
+
+
+class BloomFilter(_Filter):
+    """Sectorized filter (bf_create): keys and results are torch tensors on the GPU."""
+
+    def __init__(self, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
+                 k: int = 8, seed: int = 0):
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.seed = seed
+        st, h = bf_create(num_blocks, words_per_block, word_bits, k, seed)
+        self._adopt(st, h, "bf_create")
+
+
+class ClassicFilter(_Filter):
+    """Classic filter of num_bits bits (bf_create_classic)."""
+
+    def __init__(self, num_bits: int, k: int = 8, seed: int = 0):
+        self.num_bits = num_bits
+        self.seed = seed
+        st, h = bf_create_classic(num_bits, k, seed)
+        self._adopt(st, h, "bf_create_classic")
+
+
+class CacheSectorizedFilter(_Filter):
+    """Cache-sectorized filter with z = groups word groups (bf_create_csbf)."""
+
+    def __init__(self, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
+                 groups: int = 2, k: int = 8, seed: int = 0):
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.groups = groups
+        self.seed = seed
+        st, h = bf_create_csbf(num_blocks, words_per_block, word_bits, groups, k, seed)
+        self._adopt(st, h, "bf_create_csbf")
 
 
 class BatchPlan:

@@ -79,6 +79,7 @@ bf_mapping_t default_mapping(const bf_filter* f, int op) {
 }
 
 bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
+  if (f->layout != BF_LAYOUT_SECTORIZED) return variant_resolve_mapping(f, op);
   bf_mapping_t m = f->mapping[op];
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     const uint32_t cap = m.max_workgroups;
@@ -101,6 +102,7 @@ bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
 }
 
 bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
+  if (f->layout != BF_LAYOUT_SECTORIZED) return variant_validate_mapping(f, op, m);
   if (m.strategy > BF_STRATEGY_PARTITIONED) return BF_EINVAL;
   if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
@@ -121,22 +123,10 @@ bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
   return BF_OK;
 }
 
-// Strategy of one bulk add: partitioned when asked for, or (auto) when the
-// filter has enough 64 KiB chunks to occupy every CU (one workgroup owns a
-// chunk) and the batch is dense enough for streaming the touched chunks to
-// beat one memory-side atomic group per key (~40 B of record traffic per
-// key plus two passes over the filter, against ~50 ps per key of atomic
-// request rate).
-bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
-  if (m.strategy == BF_STRATEGY_DIRECT) return false;
-  if (!partition_applicable(f, n)) return false;
-  if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
-  const uint64_t chunks = f->nbytes / (64 * 1024);
-  return chunks >= 512 && n >= (1ull << 21) && n >= f->nbytes / 48;
-}
-
 bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                  void* stream) {
+  if (f->layout != BF_LAYOUT_SECTORIZED)
+    return variant_launch(f, op, keys, n, out, static_cast<hipStream_t>(stream));
   ensure_registry();
   bf_mapping_t m = resolve_mapping(f, op);
   if (op == BF_OP_ADD && use_partitioned(f, n, f->mapping[BF_OP_ADD]))
@@ -198,25 +188,8 @@ bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
 
 }  // namespace
 
-extern "C" {
-
-bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits, uint32_t k,
-                    uint64_t seed, bf_filter** out) {
-  if (out == nullptr) return BF_EINVAL;
-  const uint32_t s = words_per_block;
-  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
-  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
-  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
-  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
-
-  bf_filter* f = new (std::nothrow) bf_filter{};
-  if (f == nullptr) return BF_ENOMEM;
-  f->num_blocks = num_blocks;
-  f->s = s;
-  f->word_bits = word_bits;
-  f->k = k;
-  f->seed = seed;
-  f->nbytes = num_blocks * s * (word_bits / 8);
+bf_status bfhip::alloc_filter_words(bf_filter* f) {
+  f->num_bits = f->nbytes * 8;
   if (hipGetDevice(&f->device) != hipSuccess) {
     delete f;
     return BF_EDEVICE;
@@ -232,6 +205,45 @@ bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word
     delete f;
     return BF_EDEVICE;
   }
+  return BF_OK;
+}
+
+// Strategy of one bulk add: partitioned when asked for, or (auto) when the
+// filter has enough 64 KiB chunks to occupy every CU (one workgroup owns a
+// chunk) and the batch is dense enough for streaming the touched chunks to
+// beat one memory-side atomic group per key (~40 B of record traffic per
+// key plus two passes over the filter, against ~50 ps per key of atomic
+// request rate).
+bool bfhip::use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
+  if (m.strategy == BF_STRATEGY_DIRECT) return false;
+  if (!partition_applicable(f, n)) return false;
+  if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
+  const uint64_t chunks = f->nbytes / (64 * 1024);
+  return chunks >= 512 && n >= (1ull << 21) && n >= f->nbytes / 48;
+}
+
+extern "C" {
+
+bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits, uint32_t k,
+                    uint64_t seed, bf_filter** out) {
+  if (out == nullptr) return BF_EINVAL;
+  const uint32_t s = words_per_block;
+  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
+  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
+  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
+  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
+
+  bf_filter* f = new (std::nothrow) bf_filter{};
+  if (f == nullptr) return BF_ENOMEM;
+  f->layout = BF_LAYOUT_SECTORIZED;
+  f->num_blocks = num_blocks;
+  f->s = s;
+  f->word_bits = word_bits;
+  f->k = k;
+  f->seed = seed;
+  f->nbytes = num_blocks * s * (word_bits / 8);
+  const bf_status st = alloc_filter_words(f);
+  if (st != BF_OK) return st;
   *out = f;
   return BF_OK;
 }
@@ -296,6 +308,9 @@ bf_status bf_info(const bf_filter* f, bf_info_t* out) {
   i.d_words = f->d_words;
   i.mapping[BF_OP_ADD] = resolve_mapping(f, BF_OP_ADD);
   i.mapping[BF_OP_CONTAINS] = resolve_mapping(f, BF_OP_CONTAINS);
+  i.layout = f->layout;
+  i.groups = f->groups;
+  i.num_bits = f->num_bits;
   *out = i;
   return BF_OK;
 }

@@ -76,6 +76,42 @@ __device__ __forceinline__ constexpr uint32_t salt() {
 // (the salts are odd by construction).
 static_assert((kSalts.a[0] & kSalts.a[31] & 1u) == 1u, "salts are odd");
 
+// Classic filter (Sec. II-A-1): the same derivation kept at 64 bits,
+// A_j = xxHash64(LE64(j), salt seed) | 1; the low halves are the a_j above.
+struct Salt64Table {
+  uint64_t a[kMaxK];
+};
+
+__host__ __device__ constexpr Salt64Table make_salts64() {
+  Salt64Table t{};
+  for (int j = 0; j < kMaxK; ++j)
+    t.a[j] = xxh64_u64(static_cast<uint64_t>(j), xxh64_u64_init(kSaltSeed)) | 1ull;
+  return t;
+}
+
+constexpr Salt64Table kSalts64 = make_salts64();
+static_assert(static_cast<uint32_t>(kSalts64.a[7]) == kSalts.a[7], "salt halves");
+
+// Cache-sectorized filter (Sec. II-A-5 with the group index of Sec. V-A):
+// one further odd multiplier per group, c_g = (xxHash64(LE64(32 + g), salt
+// seed) mod 2^32) | 1, g < 16, picks the word of group g.
+constexpr int kMaxGroups = 16;
+
+struct GroupSaltTable {
+  uint32_t c[kMaxGroups];
+};
+
+__host__ __device__ constexpr GroupSaltTable make_group_salts() {
+  GroupSaltTable t{};
+  for (int g = 0; g < kMaxGroups; ++g)
+    t.c[g] = static_cast<uint32_t>(
+                 xxh64_u64(static_cast<uint64_t>(kMaxK + g), xxh64_u64_init(kSaltSeed))) |
+             1u;
+  return t;
+}
+
+constexpr GroupSaltTable kGroupSalts = make_group_salts();
+
 // Block of a hash: floor(hi32 * b / 2^32) for 1 <= b <= 2^32.  The block
 // count is split as b = nb_hi * 2^32 + nb_lo with nb_hi in {0, 1}; then the
 // product's high word is umulhi(hi, nb_lo) + nb_hi * hi.

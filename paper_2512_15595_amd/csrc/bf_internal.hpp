@@ -19,6 +19,9 @@ struct bf_filter {
   bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
   void* scratch;            // partitioned-construction workspace (grow-only)
   uint64_t scratch_bytes;
+  uint32_t layout;          // BF_LAYOUT_*
+  uint32_t groups;          // cache-sectorized z, else 0
+  uint64_t num_bits;        // nbytes * 8
 };
 
 namespace bfhip {
@@ -43,4 +46,17 @@ dim3 part_grid1(const PartArgs& a);
 dim3 part_grid2(const PartArgs& a);
 dim3 part_grid3(const PartArgs& a);
 __global__ void part_zero_kernel(unsigned long long* p, uint64_t n);
+
+// Filter allocation shared by every create call (bf_api.hip): fills nbytes,
+// device, d_words (zeroed, synchronously).  On error the handle is freed.
+bf_status alloc_filter_words(bf_filter* f);
+
+// Whether a bulk add of n keys takes the partitioned strategy (bf_api.hip).
+bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m);
+
+// The classic and cache-sectorized layouts (bf_variants.hip).
+bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op);
+bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m);
+bf_status variant_launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
+                         hipStream_t stream);
 }  // namespace bfhip

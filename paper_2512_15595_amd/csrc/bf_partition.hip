@@ -7,6 +7,7 @@
 #include <cmath>
 
 #include "bf_internal.hpp"
+#include "bf_variant_registry.hpp"
 #include "bf_partition.hpp"
 #include "bf_registry.hpp"
 
@@ -85,6 +86,13 @@ void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
 }
 
 PartKernels part_kernels(const bf_filter* f) {
+  if (f->layout == BF_LAYOUT_CACHE_SECTORIZED) {
+    ensure_variant_registry();
+    const VariantRegistry& r = variant_registry();
+    const int idx = csbf_part_index(static_cast<int>(f->word_bits), static_cast<int>(f->s),
+                                    static_cast<int>(f->groups), k_index(f->k));
+    return PartKernels{r.csbf_part1[idx], r.csbf_part2[idx], r.csbf_apply[idx]};
+  }
   ensure_registry();
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
@@ -114,6 +122,7 @@ dim3 part_grid3(const PartArgs& a) {
 }
 
 bool partition_applicable(const bf_filter* f, uint64_t n) {
+  if (f->layout == BF_LAYOUT_CLASSIC) return false;
   PartArgs a{};
   PartLayout L{};
   const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
@@ -149,7 +158,8 @@ bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStr
   a.nb_lo = static_cast<uint32_t>(f->num_blocks);
   a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
   a.nfilters = 1;
-  a.k = f->k;
+  // the cache-sectorized rule takes the bits per selected word
+  a.k = f->layout == BF_LAYOUT_CACHE_SECTORIZED ? f->k / f->groups : f->k;
   a.keys = keys;
   return part_launch(a, L, k, stream);
 }

@@ -31,6 +31,7 @@
 
 #include "bf_hash.hpp"
 #include "bf_kernels.hpp"
+#include "bf_variant_kernels.hpp"
 
 namespace bfhip {
 
@@ -121,6 +122,48 @@ __device__ __forceinline__ uint64_t bucket2_cap(const PartArgs& a, uint64_t c) {
 __device__ __forceinline__ uint32_t rec_block(uint64_t r) { return static_cast<uint32_t>(r >> 32); }
 __device__ __forceinline__ uint32_t rec_lo(uint64_t r) { return static_cast<uint32_t>(r); }
 
+template <typename W>
+__device__ __forceinline__ void lds_or(W* p, W v) {
+  if constexpr (sizeof(W) == 8)
+    atomicOr(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
+  else
+    atomicOr(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(v));
+}
+
+// What a record does to its block, per layout: Z = 0 is the sectorized
+// filter (every word of the block gets its pattern), Z > 0 the
+// cache-sectorized filter with Z groups (one word per group; `k` then
+// carries the bits per selected word).  add_global is the direct fallback
+// (device-scope atomics), add_lds the apply step on a block held in LDS.
+template <typename W, int S_WORDS, int K, int Z>
+struct BlockRule {
+  CsbfLane<W, S_WORDS, Z, K, 1> ln;
+  __device__ __forceinline__ BlockRule() : ln(0) {}
+  __device__ __forceinline__ void add_global(W* words, uint32_t blk, uint32_t lo, uint32_t k) const {
+    csbf_add_block<W, S_WORDS, Z, K, 1>(words, blk, lo, ln, k);
+  }
+  __device__ __forceinline__ void add_lds(W* block, uint32_t lo, uint32_t k) const {
+#pragma unroll
+    for (int i = 0; i < Z; ++i) lds_or<W>(&block[ln.word(i, lo)], ln.pattern(i, lo, k));
+  }
+};
+
+template <typename W, int S_WORDS, int K>
+struct BlockRule<W, S_WORDS, K, 0> {
+  LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp;
+  __device__ __forceinline__ BlockRule() : lp(0) {}
+  __device__ __forceinline__ void add_global(W* words, uint32_t blk, uint32_t lo, uint32_t k) const {
+    add_block<W, S_WORDS, K, 1, S_WORDS, false>(words, blk, lo, lp, k);
+  }
+  __device__ __forceinline__ void add_lds(W* block, uint32_t lo, uint32_t k) const {
+#pragma unroll
+    for (int f = 0; f < S_WORDS; ++f) {
+      const W pat = lp.word(0, f, lo, k);
+      if (pat) lds_or<W>(&block[f], pat);
+    }
+  }
+};
+
 // Words and local block of a record's global block (direct fallback).
 template <typename W>
 __device__ __forceinline__ W* record_target(const PartArgs& a, uint32_t gblock, uint32_t& local) {
@@ -195,7 +238,7 @@ __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], cons
 }
 
 // First pass: hash keys and group the records by high digit.
-template <typename W, int S_WORDS, int K>
+template <typename W, int S_WORDS, int K, int Z = 0>
 __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) uint64_t stage[kPartStep];
   __shared__ uint32_t cnt[kMaxDigits];
@@ -203,7 +246,7 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a)
   __shared__ uint64_t base[kMaxDigits];
   for (uint32_t d = threadIdx.x; d < a.f1; d += kPartThreads) cnt[d] = 0;
   __syncthreads();
-  const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
+  const BlockRule<W, S_WORDS, K, Z> rule;
   const uint32_t shift = a.chunk_shift + a.low_bits;
   const uint64_t begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
   const uint64_t end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
@@ -255,14 +298,14 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a)
         [&](uint64_t v) {
           uint32_t local;
           W* w = record_target<W>(a, rec_block(v), local);
-          add_block<W, S_WORDS, K, 1, S_WORDS, false>(w, local, rec_lo(v), lp, a.k);
+          rule.add_global(w, local, rec_lo(v), a.k);
         });
   }
 }
 
 // Second pass: workgroup (d1, qi) groups the qi-th slice of high-digit
 // bucket d1 by chunk.
-template <typename W, int S_WORDS, int K>
+template <typename W, int S_WORDS, int K, int Z = 0>
 __global__ __launch_bounds__(kPartThreads) void part_scatter2_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) uint64_t stage[kPartStep];
   __shared__ uint32_t cnt[kMaxDigits];
@@ -270,7 +313,7 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter2_kernel(PartArgs a)
   __shared__ uint64_t base[kMaxDigits];
   for (uint32_t d = threadIdx.x; d < a.f2; d += kPartThreads) cnt[d] = 0;
   __syncthreads();
-  const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
+  const BlockRule<W, S_WORDS, K, Z> rule;
   uint32_t d1, qi, nq;
   if (a.work2) {
     if (blockIdx.x >= a.nwork2) return;
@@ -307,27 +350,19 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter2_kernel(PartArgs a)
         [&](uint64_t v) {
           uint32_t local;
           W* w = record_target<W>(a, rec_block(v), local);
-          add_block<W, S_WORDS, K, 1, S_WORDS, false>(w, local, rec_lo(v), lp, a.k);
+          rule.add_global(w, local, rec_lo(v), a.k);
         });
   }
 }
 
-template <typename W>
-__device__ __forceinline__ void lds_or(W* p, W v) {
-  if constexpr (sizeof(W) == 8)
-    atomicOr(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
-  else
-    atomicOr(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(v));
-}
-
 // Apply: one workgroup per chunk (grid-stride).  Loads and records are
 // handled four at a time per thread so that enough requests are in flight.
-template <typename W, int S_WORDS, int K>
+template <typename W, int S_WORDS, int K, int Z = 0>
 __global__ __launch_bounds__(kApplyThreads) void part_apply_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) uint32_t lds_raw[kChunkBytes / 4];
   W* lds = reinterpret_cast<W*>(lds_raw);
   u32x4* lvec = reinterpret_cast<u32x4*>(lds_raw);
-  const LanePatterns<W, S_WORDS, K, 1, S_WORDS> lp(0);
+  const BlockRule<W, S_WORDS, K, Z> rule;
   const uint32_t blocks_per_chunk = 1u << a.chunk_shift;
   const uint32_t local_mask = blocks_per_chunk - 1;
   constexpr int kU = 4;
@@ -388,12 +423,7 @@ __global__ __launch_bounds__(kApplyThreads) void part_apply_kernel(PartArgs a) {
       for (int u = 0; u < kU; ++u) {
         if (i + static_cast<uint64_t>(u) * kApplyThreads < count) {
           const uint32_t lb = rec_block(r[u]) & local_mask;
-          const uint32_t lo = rec_lo(r[u]);
-#pragma unroll
-          for (int f = 0; f < S_WORDS; ++f) {
-            const W pat = lp.word(0, f, lo, a.k);
-            if (pat) lds_or<W>(&lds[lb * S_WORDS + f], pat);
-          }
+          rule.add_lds(lds + lb * S_WORDS, rec_lo(r[u]), a.k);
         }
       }
     }

@@ -32,7 +32,8 @@ def test_headers_declare_the_boundary():
     names = set()
     for h in HEADERS:
         names |= set(_declared_functions(h))
-    for required in ("bf_create", "bf_destroy", "bf_add", "bf_contains", "bf_clear", "bf_info",
+    for required in ("bf_create", "bf_create_classic", "bf_create_csbf", "bf_destroy", "bf_add",
+                     "bf_contains", "bf_clear", "bf_info",
                      "bf_set_mapping", "bf_strerror", "bfb_random_read", "bfb_random_atomic_or",
                      "bfb_gups", "bfb_copy"):
         assert required in names
@@ -73,6 +74,35 @@ def test_binding_loads_and_validates_without_gpu():
     assert st == bf.BF_EINVAL
     assert bf.bf_strerror(bf.BF_EINVAL) == "invalid argument"
     assert bf.bf_strerror(12345) == "unknown status"
+
+
+def test_variant_layouts_validate_without_gpu():
+    _ensure_built()
+    from paper_2512_15595_amd import bf
+
+    for args in [
+        (0, 8, 0),                  # no bits
+        (96, 8, 0),                 # not a multiple of 64
+        ((1 << 40) + 64, 8, 0),     # larger than 2^40 bits
+        (1 << 20, 0, 0),            # k = 0
+        (1 << 20, 33, 0),           # k > 32
+    ]:
+        st, h = bf.bf_create_classic(*args)
+        assert st == bf.BF_EINVAL, args
+        assert not h.value
+    for args in [
+        (4096, 8, 32, 16, 16, 0),   # z > s
+        (4096, 8, 32, 3, 6, 0),     # z not a power of two
+        (4096, 8, 32, 4, 6, 0),     # k not a multiple of z
+        (4096, 8, 32, 4, 2, 0),     # k < z
+        (4096, 8, 32, 2, 34, 0),    # k > 32
+        (0, 8, 32, 2, 4, 0),        # no blocks
+        (4096, 8, 16, 2, 4, 0),     # word width
+        (4096, 6, 32, 2, 4, 0),     # words per block
+    ]:
+        st, h = bf.bf_create_csbf(*args)
+        assert st == bf.BF_EINVAL, args
+        assert not h.value
 
 
 def test_bench_library_validates_without_gpu():
