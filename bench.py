@@ -459,8 +459,9 @@ def run_cache(args) -> dict:
     keys = torch.empty(n, dtype=torch.int64, device="cuda")
     assert lib.bfb_fill_splitmix64(keys.data_ptr(), n, 31, 0, stream) == 0
     out = torch.empty(n, dtype=torch.uint8, device="cuda")
-    sizes = [1 << e for e in range(20, 29)]
-    ks = (4, 6, 8, 12, 16)
+    sizes = [1 << e for e in args.cache_log2_sizes]
+    ks = tuple(args.cache_ks)
+    layouts = tuple(args.cache_layouts)
 
     def timed(fn, reps):
         fn()
@@ -481,7 +482,7 @@ def run_cache(args) -> dict:
 
     rows = []
     for nbytes in sizes:
-        for layout in CACHE_LAYOUTS:
+        for layout in layouts:
             for k in ks:
                 f, name = make_cache_filter(bfmod, layout, nbytes, k, 7)
                 try:
@@ -496,9 +497,10 @@ def run_cache(args) -> dict:
     fbytes = 64 << 20
     fresh = torch.empty(1 << 22, dtype=torch.int64, device="cuda")
     assert lib.bfb_fill_splitmix64(fresh.data_ptr(), fresh.numel(), 32, 0, stream) == 0
-    for c_bits in (8, 16, 32):
+    for c_bits in ((8, 16, 32) if args.cache_fpr else ()):
         ins = fbytes * 8 // c_bits
-        for layout in CACHE_LAYOUTS:
+        assert ins <= n, "the accuracy pass needs 2^26 keys"
+        for layout in layouts:
             for k in ks:
                 f, name = make_cache_filter(bfmod, layout, fbytes, k, 9)
                 try:
@@ -512,10 +514,12 @@ def run_cache(args) -> dict:
                                  "fpr": fp / fresh.numel(), "classic_eq1": float(eq1)})
 
     kmer_rows = []
-    kmers = workloads.kmer_keys(n + 30, 33)
-    d_kmers = torch.from_numpy(kmers.view(np.int64)).to("cuda")
-    for nbytes in (1 << 22, 1 << 28):
-        for layout in CACHE_LAYOUTS:
+    kmer_sizes = (1 << 22, 1 << 28) if args.cache_kmer else ()
+    if kmer_sizes:
+        kmers = workloads.kmer_keys(n + 30, 33)
+        d_kmers = torch.from_numpy(kmers.view(np.int64)).to("cuda")
+    for nbytes in kmer_sizes:
+        for layout in layouts:
             f, name = make_cache_filter(bfmod, layout, nbytes, 8, 11)
             try:
                 a, c = throughput(f, d_kmers, args.steps)
@@ -524,7 +528,8 @@ def run_cache(args) -> dict:
             kmer_rows.append({"layout": name, "bytes": nbytes, "k": 8, "add_gkeys_s": round(a, 3),
                               "contains_gkeys_s": round(c, 3)})
 
-    best = max(r["contains_gkeys_s"] for r in rows if r["layout"] == "sbf_8x32" and r["k"] == 8)
+    sbf = [r["contains_gkeys_s"] for r in rows if r["layout"] == "sbf_8x32" and r["k"] == 8]
+    best = max(sbf) if sbf else None
     return {
         "metric": "Gkeys/s add / contains, cache-resident filters, per layout",
         "value": best,
@@ -538,7 +543,7 @@ def run_cache(args) -> dict:
         "dtype": "u64",
         "data": "synthetic",
         "config": {"workload": "cache_regime_1MiB_256MiB", "keys_per_op": n,
-                   "sizes_bytes": sizes, "k": list(ks), "layouts": list(CACHE_LAYOUTS),
+                   "sizes_bytes": sizes, "k": list(ks), "layouts": list(layouts),
                    "value_is": "best sbf_8x32 k=8 contains rate over sizes"},
         "throughput": rows,
         "fpr_64MiB": fpr_rows,
@@ -557,6 +562,11 @@ def main() -> int:
     ap.add_argument("--serve-coalesce-keys", type=int, default=65536)
     ap.add_argument("--workload", choices=["dram", "batched", "serve", "cache"], default="dram")
     ap.add_argument("--cache-log2-keys", type=int, default=26)
+    ap.add_argument("--cache-log2-sizes", type=int, nargs="+", default=list(range(20, 29)))
+    ap.add_argument("--cache-ks", type=int, nargs="+", default=[4, 6, 8, 12, 16])
+    ap.add_argument("--cache-layouts", type=str, nargs="+", default=list(CACHE_LAYOUTS))
+    ap.add_argument("--cache-fpr", type=int, default=1, help="0 skips the accuracy pass")
+    ap.add_argument("--cache-kmer", type=int, default=1, help="0 skips the 31-mer pass")
     ap.add_argument("--batch-filters", type=int, default=4096)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)

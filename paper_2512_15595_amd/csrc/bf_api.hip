@@ -209,17 +209,16 @@ bf_status bfhip::alloc_filter_words(bf_filter* f) {
 }
 
 // Strategy of one bulk add: partitioned when asked for, or (auto) when the
-// filter has enough 64 KiB chunks to occupy every CU (one workgroup owns a
-// chunk) and the batch is dense enough for streaming the touched chunks to
-// beat one memory-side atomic group per key (~40 B of record traffic per
-// key plus two passes over the filter, against ~50 ps per key of atomic
-// request rate).
+// batch is dense enough for streaming the touched chunks to beat one
+// memory-side atomic group per key.  Measured crossover on MI355X: about
+// 2^21 keys for filters up to 64 MiB (few chunks: the apply is split over
+// many workgroups), about filter bytes / 48 keys beyond (each touched chunk
+// is read and written once).
 bool bfhip::use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
   if (m.strategy == BF_STRATEGY_DIRECT) return false;
   if (!partition_applicable(f, n)) return false;
   if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
-  const uint64_t chunks = f->nbytes / (64 * 1024);
-  return chunks >= 512 && n >= (1ull << 21) && n >= f->nbytes / 48;
+  return n >= (1ull << 22) && n >= f->nbytes / 48;
 }
 
 extern "C" {

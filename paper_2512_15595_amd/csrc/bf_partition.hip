@@ -65,6 +65,17 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
   a.cap2 = capacity(static_cast<double>(n) / chunks, 64, 16);
   const uint64_t per_bucket = std::min<uint64_t>(a.cap1, n);
   a.q = static_cast<uint32_t>(std::clamp<uint64_t>((per_bucket + 65535) / 65536, 1, 32));
+  // A filter of few chunks (L2 or Infinity-Cache sized) leaves too few
+  // digits to fill 256 CUs: cut the second pass into more slices (at least
+  // 16 Ki records each) and split every chunk's records over several apply
+  // workgroups (at least 8 Ki records each), so that both grids reach about
+  // a thousand or two workgroups.  Split slices merge with atomic OR.
+  const uint64_t q_fill = (1024 + a.f1 - 1) / a.f1;
+  a.q = static_cast<uint32_t>(std::clamp<uint64_t>(
+      std::max<uint64_t>(a.q, std::min<uint64_t>(q_fill, per_bucket / 16384)), 1, 1024));
+  const uint64_t split_fill = (2048 + chunks - 1) / chunks;
+  a.apply_split = static_cast<uint32_t>(std::clamp<uint64_t>(
+      std::min<uint64_t>(split_fill, n / chunks / 8192), 1, 1024));
   uint64_t off = 0;
   L.off_buf1 = off;
   off = align256(off + 8ull * a.f1 * a.cap1);
@@ -117,7 +128,7 @@ bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels&
 dim3 part_grid1(const PartArgs& a) { return dim3(static_cast<uint32_t>((a.n + a.range1 - 1) / a.range1)); }
 dim3 part_grid2(const PartArgs& a) { return dim3(a.work2 ? a.nwork2 : a.f1 * a.q); }
 dim3 part_grid3(const PartArgs& a) {
-  const uint64_t items = a.work3 ? a.nwork3 : a.chunks;
+  const uint64_t items = a.work3 ? a.nwork3 : a.chunks * std::max<uint32_t>(a.apply_split, 1);
   return dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, 65535))));
 }
 

@@ -80,15 +80,40 @@ int log2_u64(uint64_t v) {
   return r;
 }
 
-// Defaults: one lane per key and two keys per lane, which keeps 2 * k
-// (classic) or 2 * z (cache-sectorized) independent requests in flight per
-// lane; every group word is then a lane-private access (Sec. V-A).
+// Defaults, from a measured sweep on MI355X (filters of 1 MiB .. 1 GiB,
+// every layout and mapping):
+//  - classic: one key per lane for add, two for contains (all k positions of
+//    both keys are in flight before any is consumed);
+//  - cache-sectorized add: THETA = z, so the z group updates of one key
+//    leave as one instruction and merge into one request per 64-byte
+//    segment (THETA = 1 issues z requests per key: up to z times slower at
+//    the atomic request rate);
+//  - cache-sectorized contains: the same for blocks larger than 32 bytes
+//    (THETA = z, at most 4 below the HBM size class and at most 8 in it);
+//    32-byte blocks below the HBM class are fastest with THETA = 1, where the
+//    z loads of a key hit one line in L2 or the Infinity Cache anyway.
 bf_mapping_t default_variant_mapping(const bf_filter* f, int op) {
   bf_mapping_t m{};
-  m.lanes_per_key = 1;
-  m.words_per_lane = f->layout == BF_LAYOUT_CLASSIC ? 1 : f->s;
-  m.keys_per_lane = 2;
   m.atomic_bits = op == BF_OP_ADD ? 32 : 0;
+  if (f->layout == BF_LAYOUT_CLASSIC) {
+    m.lanes_per_key = 1;
+    m.words_per_lane = 1;
+    m.keys_per_lane = op == BF_OP_ADD ? 1 : 2;
+    return m;
+  }
+  const uint32_t z = f->groups;
+  const bool hbm = f->nbytes > (256ull << 20);
+  const uint32_t block_bytes = f->s * f->word_bits / 8;
+  uint32_t theta = z;
+  if (op == BF_OP_CONTAINS) {
+    if (block_bytes <= 32 && !hbm)
+      theta = 1;
+    else
+      theta = z < (hbm ? 8u : 4u) ? z : (hbm ? 8u : 4u);
+  }
+  m.lanes_per_key = theta;
+  m.words_per_lane = f->s / theta;
+  m.keys_per_lane = (theta == 1 && z == 1) ? 2 : 1;
   return m;
 }
 
@@ -100,8 +125,10 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
   bf_mapping_t m = f->mapping[op];
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     const uint32_t cap = m.max_workgroups;
+    const uint32_t strategy = m.strategy;
     m = default_variant_mapping(f, op);
     m.max_workgroups = cap;
+    m.strategy = strategy;
   }
   if (f->layout == BF_LAYOUT_CACHE_SECTORIZED) {
     if (m.lanes_per_key == 0) m.lanes_per_key = 1;
@@ -117,7 +144,11 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
   }
   if (m.keys_per_lane == 0) m.keys_per_lane = 1;
   m.atomic_bits = op == BF_OP_ADD ? 32 : 0;
-  if (f->layout == BF_LAYOUT_CLASSIC || op == BF_OP_CONTAINS) m.strategy = BF_STRATEGY_AUTO;
+  // classic adds are always direct; lookups have no strategy
+  if (op == BF_OP_CONTAINS)
+    m.strategy = BF_STRATEGY_AUTO;
+  else if (f->layout == BF_LAYOUT_CLASSIC)
+    m.strategy = BF_STRATEGY_DIRECT;
   return m;
 }
 
