@@ -9,7 +9,9 @@ The filter definition follows "Optimizing Bloom Filters on Modern GPUs"
 (arXiv 2512.15595): Sec. II-A-2/3/4 for the blocked, register-blocked and
 sectorized layouts, Sec. IV-B for one xxHash64 base hash per key and salted
 multiplicative bit positions; Sec. II-A-1 for the classic (unblocked) filter
-and Sec. II-A-5 with Sec. V-A for the cache-sectorized filter.  ``bf_oracle.h`` lists the readings taken where
+and Sec. II-A-5 with Sec. V-A for the cache-sectorized filter; the chained
+pattern hashing of prior GPU filters (Sec. IV-B) for the optimization
+breakdown of Sec. V-E.  ``bf_oracle.h`` lists the readings taken where
 the paper is silent.
 """
 from __future__ import annotations
@@ -92,6 +94,10 @@ def _load():
         lib.oracle_csbf_block_words.argtypes = [u64, u32, u32, u32, u32, u64, vp, u64, vp,
                                                 u64, vp]
         lib.oracle_csbf_block_words.restype = i32
+        lib.oracle_chained_add.argtypes = [vp, u64, u32, u32, u32, u64, vp, u64]
+        lib.oracle_chained_add.restype = i32
+        lib.oracle_chained_contains.argtypes = [vp, u64, u32, u32, u32, u64, vp, u64, vp]
+        lib.oracle_chained_contains.restype = i32
         _lib = lib
     return _lib
 
@@ -314,3 +320,20 @@ def csbf_block_words(num_blocks: int, words_per_block: int, word_bits: int, grou
     if rc != 0:
         raise ValueError("bad parameters or block selection")
     return out[: sel.size]
+
+
+class ChainedOracle(OracleFilter):
+    """Sectorized filter with chained pattern hashing (prior-art rule, Sec. IV-B)."""
+
+    def add(self, keys) -> None:
+        keys = _keys(keys)
+        rc = _load().oracle_chained_add(_ptr(self.bytes), *self._args(), _ptr(keys), keys.size)
+        assert rc == 0
+
+    def contains(self, keys) -> np.ndarray:
+        keys = _keys(keys)
+        out = np.zeros(max(keys.size, 1), dtype=np.uint8)
+        rc = _load().oracle_chained_contains(_ptr(self.bytes), *self._args(), _ptr(keys),
+                                             keys.size, _ptr(out))
+        assert rc == 0
+        return out[: keys.size]

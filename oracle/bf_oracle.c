@@ -493,3 +493,45 @@ int oracle_csbf_block_words(uint64_t num_blocks, uint32_t words_per_block,
     free(slot_of);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Chained pattern hashing (prior-art rule of Sec. IV-B).                    */
+/* ------------------------------------------------------------------------ */
+
+/* Sets (do_set) or tests the k bits of one key; returns 1 iff all were set. */
+static int chained_touch(uint8_t *filter, uint64_t key, uint64_t seed, uint64_t num_blocks,
+                         uint32_t s, uint32_t S, uint32_t k, int do_set) {
+    uint64_t h = oracle_hash_key(key, seed);
+    uint64_t blk = oracle_block_index(h, num_blocks);
+    unsigned L = log2_word_bits(S);
+    int all_set = 1;
+    for (uint32_t j = 0; j < k; ++j) {
+        h = oracle_hash_key(key, h);                       /* h_{j+1} */
+        unsigned p = (uint32_t)(h & 0xFFFFFFFFULL) >> (32u - L);
+        uint64_t word_index = blk * s + j % s;
+        if (do_set)
+            set_bit(filter, word_index, S, p);
+        else if (!get_bit(filter, word_index, S, p))
+            all_set = 0;
+    }
+    return all_set;
+}
+
+int oracle_chained_add(uint8_t *filter, uint64_t num_blocks, uint32_t words_per_block,
+                       uint32_t word_bits, uint32_t k, uint64_t seed, const uint64_t *keys,
+                       uint64_t n) {
+    if (oracle_check_params(num_blocks, words_per_block, word_bits, k) != 0) return -1;
+    for (uint64_t i = 0; i < n; ++i)
+        chained_touch(filter, keys[i], seed, num_blocks, words_per_block, word_bits, k, 1);
+    return 0;
+}
+
+int oracle_chained_contains(const uint8_t *filter, uint64_t num_blocks,
+                            uint32_t words_per_block, uint32_t word_bits, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n, uint8_t *out) {
+    if (oracle_check_params(num_blocks, words_per_block, word_bits, k) != 0) return -1;
+    for (uint64_t i = 0; i < n; ++i)
+        out[i] = (uint8_t)chained_touch((uint8_t *)filter, keys[i], seed, num_blocks,
+                                        words_per_block, word_bits, k, 0);
+    return 0;
+}

@@ -132,6 +132,22 @@ int oracle_csbf_block_words(uint64_t num_blocks, uint32_t words_per_block,
                             uint64_t seed, const uint64_t *keys, uint64_t n,
                             const uint64_t *sel, uint64_t nsel, uint8_t *out);
 
+/* ------------------------------------------------------------------------
+ * Sectorized filter with chained pattern hashing: the pattern rule of prior
+ * GPU filters that Sec. IV-B replaces (one initial hash, then the key hashed
+ * again with the previous hash as the seed).  Used for the optimization
+ * breakdown of Sec. V-E.  Readings: h_0 = XXH64(LE64(x), seed) selects the
+ * block as in the sectorized filter; h_{j+1} = XXH64(LE64(x), h_j); bit j
+ * (j < k) is the top log2(S) bits of lo32(h_{j+1}), in word j mod s.
+ * Parameters and layout as the sectorized filter.
+ * ------------------------------------------------------------------------ */
+int oracle_chained_add(uint8_t *filter, uint64_t num_blocks, uint32_t words_per_block,
+                       uint32_t word_bits, uint32_t k, uint64_t seed, const uint64_t *keys,
+                       uint64_t n);
+int oracle_chained_contains(const uint8_t *filter, uint64_t num_blocks,
+                            uint32_t words_per_block, uint32_t word_bits, uint32_t k,
+                            uint64_t seed, const uint64_t *keys, uint64_t n, uint8_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -128,3 +128,23 @@ def csbf_build(keys, b: int, s: int, S: int, z: int, k: int, seed: int) -> set:
     for x in keys:
         bits |= csbf_triples_of_key(int(x), b, s, S, z, k, seed)
     return bits
+
+
+# -- chained pattern hashing (prior-art rule of Sec. IV-B) -------------------
+
+def chained_triples_of_key(key: int, b: int, s: int, S: int, k: int, seed: int) -> set:
+    h = base_hash(key, seed)
+    blk = (h >> 32) * b // 2**32
+    L = S.bit_length() - 1
+    out = set()
+    for j in range(k):
+        h = base_hash(key, h)
+        out.add((blk, j % s, (h & M32) >> (32 - L)))
+    return out
+
+
+def chained_build(keys, b: int, s: int, S: int, k: int, seed: int) -> set:
+    bits = set()
+    for x in keys:
+        bits |= chained_triples_of_key(int(x), b, s, S, k, seed)
+    return bits

@@ -379,3 +379,60 @@ def test_csbf_model_pins():
     # one key, s = 4 words in one group, k = 1: same block (1/b), same word (1/4),
     # same bit (1/S)
     assert math.isclose(fpr_model.csbf_fpr(1, 10, 4, 32, 1, 1), 1 / 10 / 4 / 32, rel_tol=1e-12)
+
+
+# --------------------------------------------------------------------------
+# Chained pattern hashing (the prior-art rule of Sec. IV-B)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s,S", [(1, 32), (4, 64), (8, 32), (16, 64)])
+def test_chained_bits_equal_brute_force(s, S):
+    rng = _rng(400 + s + S)
+    for b in (1, 3, 17):
+        for k in sorted({s, 2 * s, 16}):
+            if k < s or k > 32:
+                continue
+            n = int(rng.integers(0, 120))
+            seed = int(rng.integers(0, 2**64, dtype=np.uint64))
+            keys = rng.integers(0, 2**64, size=n, dtype=np.uint64)
+            f = oracle.ChainedOracle(b, s, S, k, seed)
+            f.add(keys)
+            bits = brute.chained_build(keys, b, s, S, k, seed)
+            assert brute.triples_of_bytes(f.bytes, s, S) == bits
+            queries = np.concatenate([keys, rng.integers(0, 2**64, size=200, dtype=np.uint64)])
+            want = [int(brute.chained_triples_of_key(int(q), b, s, S, k, seed) <= bits)
+                    for q in queries]
+            assert f.contains(queries).tolist() == want
+
+
+def test_chained_block_rule_is_the_sectorized_one():
+    """Only the pattern differs: a one-key chained filter sets bits in the
+    same block as the sectorized filter, and its bits differ from it."""
+    for key in _keys(50, 9):
+        a = oracle.ChainedOracle(97, 4, 32, 8, 5)
+        a.add([key])
+        b = oracle.OracleFilter(97, 4, 32, 8, 5)
+        b.add([key])
+        ba = np.nonzero(a.bytes.reshape(97, 16).any(axis=1))[0]
+        bb = np.nonzero(b.bytes.reshape(97, 16).any(axis=1))[0]
+        assert ba.tolist() == bb.tolist()
+    assert not np.array_equal(a.bytes, b.bytes)
+
+
+@pytest.mark.parametrize("s,S,k,b,n", [(4, 64, 16, 512, 12000), (8, 32, 8, 1024, 24000)])
+def test_chained_fpr_matches_closed_form(s, S, k, b, n):
+    """Positions from independent full hashes are uniform: the sectorized
+    closed form applies unchanged."""
+    p = fpr_model.sbf_fpr(n, b, s, S, k)
+    R = 6
+    queries = max(200_000, int(math.ceil(2e4 / (R * p))))
+    rates = []
+    for r in range(R):
+        rng = _rng(7000 + r)
+        f = oracle.ChainedOracle(b, s, S, k, int(rng.integers(0, 2**64, dtype=np.uint64)))
+        f.add(rng.integers(0, 2**64, size=n, dtype=np.uint64))
+        rates.append(float(f.contains(rng.integers(0, 2**64, size=queries,
+                                                   dtype=np.uint64)).mean()))
+    rates = np.array(rates)
+    se = rates.std(ddof=1) / math.sqrt(R)
+    assert abs(rates.mean() - p) <= 4 * se + 0.01 * p, (rates.mean(), p, se)
