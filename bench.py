@@ -551,6 +551,105 @@ def run_cache(args) -> dict:
     }
 
 
+def run_breakdown(args) -> dict:
+    """Optimization breakdown (the analog of the paper's Sec. V-E figure) at
+    the paper's parameters, S = 64, k = 16, B = 256 (s = 4), for an
+    L2-resident (2 MiB) and an HBM-resident (1 GiB) filter: add then lookup of
+    2^log2_keys uniform keys, each step of the sequence measured on its own:
+      1 classic filter of the same size;
+      2 sectorized, chained pattern hashing, one lane per key, direct add;
+      3 + multiplicative pattern hashing (one lane per key, direct add);
+      4 + horizontal add with the hash shared by the group (best THETA in
+        {2, 4}, direct add); lookup keeps one lane per key;
+      5 + MI355X: keys per lane and, for dense adds, partitioned construction
+        (the library defaults)."""
+    import ctypes
+
+    import torch
+
+    from paper_2512_15595_amd import bf as bfmod
+
+    lib = ctypes.CDLL(bfmod.LIB_PATH)
+    vp, u64 = ctypes.c_void_p, ctypes.c_uint64
+    lib.bfb_fill_splitmix64.argtypes = [vp, u64, u64, u64, vp]
+    stream = torch.cuda.current_stream().cuda_stream
+    n = 1 << args.breakdown_log2_keys
+    keys = torch.empty(n, dtype=torch.int64, device="cuda")
+    assert lib.bfb_fill_splitmix64(keys.data_ptr(), n, 41, 0, stream) == 0
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s, S, k = 4, 64, 16
+    A, C = bfmod.BF_OP_ADD, bfmod.BF_OP_CONTAINS
+    DIRECT = bfmod.BF_STRATEGY_DIRECT
+
+    def timed(fn):
+        fn()
+        t = Timer(torch)
+        with t:
+            for _ in range(args.steps):
+                fn()
+        torch.cuda.synchronize()
+        return t.ms() / args.steps
+
+    def rates(f):
+        f.clear()
+        a = n / timed(lambda: f.add(keys)) / 1e6
+        c = n / timed(lambda: f.contains(keys, out=out)) / 1e6
+        assert int(out.sum().item()) == n, "false negative"
+        return a, c
+
+    rows = []
+    for nbytes in (2 << 20, 1 << 30):
+        b = nbytes // (s * S // 8)
+        res = {}
+        f = bfmod.ClassicFilter(nbytes * 8, k, 3)
+        res["1_classic"] = rates(f)
+        f.close()
+        f = bfmod.ChainedHashFilter(b, s, S, k, 3)
+        res["2_sectorized_chained_hash"] = rates(f)
+        f.close()
+        f = bfmod.BloomFilter(b, s, S, k, 3)
+        f.set_mapping(A, 1, s, 1, 0, 0, DIRECT)
+        f.set_mapping(C, 1, s, 1)
+        res["3_multiplicative_hash"] = rates(f)
+        best = None
+        for theta in (2, 4):
+            f.set_mapping(A, theta, s // theta, 1, 0, 0, DIRECT)
+            a, _ = rates(f)
+            if best is None or a > best[0]:
+                best = (a, theta)
+        res["4_horizontal_shared_add"] = (best[0], res["3_multiplicative_hash"][1])
+        f.set_mapping(A, 0, 0, 0)
+        f.set_mapping(C, 0, 0, 0)
+        res["5_mi355x_defaults"] = rates(f)
+        info = f.info()
+        f.close()
+        base = res["1_classic"]
+        for step, (a, c) in res.items():
+            rows.append({"filter_bytes": nbytes, "step": step, "add_gkeys_s": round(a, 3),
+                         "contains_gkeys_s": round(c, 3),
+                         "add_vs_classic": round(a / base[0], 2),
+                         "contains_vs_classic": round(c / base[1], 2)})
+            log(f"[breakdown] {nbytes >> 20} MiB {step}: add {a:.2f} contains {c:.2f} Gkeys/s")
+        rows[-2]["theta"] = best[1]
+        rows[-1]["mapping"] = {"add": info.mapping[A].as_dict(), "contains": info.mapping[C].as_dict()}
+    return {
+        "metric": "Gkeys/s add / contains along the optimization sequence",
+        "value": rows[-1]["add_gkeys_s"],
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "breakdown_sbf_4x64_k16_2MiB_1GiB", "keys_per_op": n,
+                   "value_is": "1 GiB add rate with the library defaults"},
+        "rows": rows,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--serve-filters", type=int, default=64)
@@ -560,7 +659,9 @@ def main() -> int:
     ap.add_argument("--serve-inflight", type=int, default=16)
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-coalesce-keys", type=int, default=65536)
-    ap.add_argument("--workload", choices=["dram", "batched", "serve", "cache"], default="dram")
+    ap.add_argument("--workload", choices=["dram", "batched", "serve", "cache", "breakdown"],
+                    default="dram")
+    ap.add_argument("--breakdown-log2-keys", type=int, default=26)
     ap.add_argument("--cache-log2-keys", type=int, default=26)
     ap.add_argument("--cache-log2-sizes", type=int, nargs="+", default=list(range(20, 29)))
     ap.add_argument("--cache-ks", type=int, nargs="+", default=[4, 6, 8, 12, 16])
@@ -606,6 +707,9 @@ def main() -> int:
         return 0
     if args.workload == "cache":
         print(json.dumps(run_cache(args)), flush=True)
+        return 0
+    if args.workload == "breakdown":
+        print(json.dumps(run_breakdown(args)), flush=True)
         return 0
     n = 1 << args.log2_keys
     s, S, k = args.words_per_block, args.word_bits, args.k

@@ -98,6 +98,7 @@ typedef struct {
 #define BF_LAYOUT_SECTORIZED 0       /* Sec. II-A-4 (s = 1: register-blocked) */
 #define BF_LAYOUT_CLASSIC 1          /* Sec. II-A-1: k positions over m bits */
 #define BF_LAYOUT_CACHE_SECTORIZED 2 /* Sec. II-A-5: one word per group of s/z */
+#define BF_LAYOUT_SECTORIZED_CHAINED 3 /* sectorized, chained pattern hashing (Sec. IV-B prior art) */
 
 typedef struct {
   uint64_t num_blocks;     /* 0 for the classic layout */

@@ -1,5 +1,5 @@
 /*
- * bf_variants.h -- C ABI: the two filter layouts beside the sectorized one.
+ * bf_variants.h -- C ABI: the filter layouts beside the sectorized one.
  *
  * Filters made here are used through the calls of bf.h (bf_add,
  * bf_contains, bf_clear, bf_export_words, bf_import_words, bf_info,
@@ -7,10 +7,10 @@
  * streams, errors and concurrency.  They are not accepted by batched plans
  * (bf_batch.h) or servers (bf_serve.h), which give BF_EUNSUPPORTED.  Adds
  * to a cache-sectorized filter choose between the direct and the
- * partitioned strategy as bf.h describes; classic-filter adds are always
- * direct (BF_STRATEGY_PARTITIONED gives BF_EUNSUPPORTED).
+ * partitioned strategy as bf.h describes; classic and chained-hash adds are
+ * always direct (BF_STRATEGY_PARTITIONED gives BF_EUNSUPPORTED).
  *
- * Both layouts take the per-key base hash h = xxHash64 of the key's 8
+ * Every layout takes the per-key base hash h = xxHash64 of the key's 8
  * little-endian bytes with the filter seed (paper Sec. IV-B).
  */
 #ifndef BF_VARIANTS_H
@@ -49,6 +49,17 @@ bf_status bf_create_classic(uint64_t num_bits, uint32_t k, uint64_t seed, bf_fil
  * strategy as bf.h. */
 bf_status bf_create_csbf(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits,
                          uint32_t groups, uint32_t k, uint64_t seed, bf_filter **out);
+
+/* Sectorized filter with chained pattern hashing, the rule of prior GPU
+ * filters that Sec. IV-B replaces by multiplicative hashing; kept as the
+ * baseline of the optimization breakdown (Sec. V-E).  Layout, parameters and
+ * block rule as bf_create; bit j (j < k) is the top log2(S) bits of
+ * lo32(h_{j+1}) with h_{j+1} = xxHash64(LE64(key), seed = h_j), h_0 the
+ * base hash, in word j mod s.  One lane per key; the only mapping is the
+ * default (set_mapping accepts lanes_per_key = 1, words_per_lane = s,
+ * keys_per_lane = 1) and adds are always direct. */
+bf_status bf_create_chained(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits,
+                            uint32_t k, uint64_t seed, bf_filter **out);
 
 #ifdef __cplusplus
 }

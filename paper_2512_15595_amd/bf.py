@@ -37,6 +37,7 @@ BF_STRATEGY_PARTITIONED = 2
 BF_LAYOUT_SECTORIZED = 0
 BF_LAYOUT_CLASSIC = 1
 BF_LAYOUT_CACHE_SECTORIZED = 2
+BF_LAYOUT_SECTORIZED_CHAINED = 3
 
 
 class bf_mapping_t(ctypes.Structure):
@@ -77,6 +78,8 @@ _lib.bf_create_classic.argtypes = [_u64, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create_classic.restype = _i32
 _lib.bf_create_csbf.argtypes = [_u64, _u32, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create_csbf.restype = _i32
+_lib.bf_create_chained.argtypes = [_u64, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create_chained.restype = _i32
 _lib.bf_destroy.argtypes = [_vp]
 _lib.bf_destroy.restype = _i32
 _lib.bf_add.argtypes = [_vp, _vp, _u64, _vp]
@@ -216,6 +219,14 @@ def bf_create_csbf(num_blocks: int, words_per_block: int, word_bits: int, groups
     h = _vp()
     st = _lib.bf_create_csbf(num_blocks, words_per_block, word_bits, groups, k,
                              seed & (2**64 - 1), ctypes.byref(h))
+    return st, h
+
+
+def bf_create_chained(num_blocks: int, words_per_block: int, word_bits: int, k: int, seed: int):
+    """Returns (status, handle)."""
+    h = _vp()
+    st = _lib.bf_create_chained(num_blocks, words_per_block, word_bits, k, seed & (2**64 - 1),
+                                ctypes.byref(h))
     return st, h
 
 
@@ -413,6 +424,19 @@ class ClassicFilter(_Filter):
         self.seed = seed
         st, h = bf_create_classic(num_bits, k, seed)
         self._adopt(st, h, "bf_create_classic")
+
+
+class ChainedHashFilter(_Filter):
+    """Sectorized filter with chained pattern hashing (bf_create_chained)."""
+
+    def __init__(self, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
+                 k: int = 8, seed: int = 0):
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.seed = seed
+        st, h = bf_create_chained(num_blocks, words_per_block, word_bits, k, seed)
+        self._adopt(st, h, "bf_create_chained")
 
 
 class CacheSectorizedFilter(_Filter):

@@ -133,7 +133,7 @@ dim3 part_grid3(const PartArgs& a) {
 }
 
 bool partition_applicable(const bf_filter* f, uint64_t n) {
-  if (f->layout == BF_LAYOUT_CLASSIC) return false;
+  if (f->layout != BF_LAYOUT_SECTORIZED && f->layout != BF_LAYOUT_CACHE_SECTORIZED) return false;
   PartArgs a{};
   PartLayout L{};
   const uint32_t shift = part_chunk_shift(f->s, f->word_bits);

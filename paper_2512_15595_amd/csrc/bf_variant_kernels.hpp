@@ -25,6 +25,12 @@
 // of s/THETA words that contains whole groups, which is the s/z <= Phi rule
 // of Sec. V-A, so the word choice never crosses lanes.  (block, lo32) is
 // broadcast within the group and a lookup's group AND is one ballot.
+//
+// Chained pattern hashing (the prior-art rule of Sec. IV-B, kept for the
+// optimization breakdown of Sec. V-E): the sectorized layout and block rule,
+// but bit j comes from h_{j+1} = xxHash64(key, seed = h_j) -- k dependent
+// hash evaluations per key instead of k independent multiplies.  One lane
+// per key, whole-block loads / one atomic per word.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,6 +40,7 @@
 
 #include "bf_hash.hpp"
 #include "bf_kernels.hpp"
+#include "bf_registry.hpp"
 
 namespace bfhip {
 
@@ -355,6 +362,57 @@ __global__ __launch_bounds__(kBlockThreads) void csbf_contains_kernel(BfArgs a) 
     const uint32_t count = static_cast<uint32_t>(a.n - base < kTile ? a.n - base : kTile);
     csbf_contains_tile<W, S_WORDS, Z, K, THETA, KT>(fv, a.keys + base, a.out + base, count,
                                                     count == kTile, a.k, ln);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Chained pattern hashing
+// ---------------------------------------------------------------------------
+template <typename W, int S_WORDS, int K>
+__device__ __forceinline__ void chained_pattern(uint64_t key, uint64_t h, uint32_t k,
+                                                W (&pat)[S_WORDS]) {
+#pragma unroll
+  for (int f = 0; f < S_WORDS; ++f) pat[f] = 0;
+  if constexpr (K > 0) {
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      h = xxh64_u64(key, xxh64_u64_init(h));
+      pat[j % S_WORDS] |= W(1) << (static_cast<uint32_t>(h) >> (32 - WordBits<W>::kLog2));
+    }
+  } else {
+    for (uint32_t j = 0; j < k; ++j) {
+      h = xxh64_u64(key, xxh64_u64_init(h));
+      const W bit = W(1) << (static_cast<uint32_t>(h) >> (32 - WordBits<W>::kLog2));
+      const uint32_t w = j & (S_WORDS - 1);
+#pragma unroll
+      for (int f = 0; f < S_WORDS; ++f) pat[f] |= (w == static_cast<uint32_t>(f)) ? bit : W(0);
+    }
+  }
+}
+
+template <typename W, int S_WORDS, int K, int OP>
+__global__ __launch_bounds__(kBlockThreads) void chained_kernel(BfArgs a) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kBlockThreads;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kBlockThreads + threadIdx.x; i < a.n;
+       i += stride) {
+    const uint64_t key = a.keys[i];
+    const uint64_t h = xxh64_u64(key, a.hash_init);
+    const uint32_t blk = block_of(h, a.nb_lo, a.nb_hi_mask);
+    W pat[S_WORDS];
+    chained_pattern<W, S_WORDS, K>(key, h, a.k, pat);
+    W* base = static_cast<W*>(a.words) + static_cast<uint64_t>(blk) * S_WORDS;
+    if constexpr (OP == kOpAdd) {
+#pragma unroll
+      for (int f = 0; f < S_WORDS; ++f)
+        __hip_atomic_fetch_or(base + f, pat[f], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      W v[S_WORDS];
+      load_words<W, S_WORDS>(base, v);
+      W miss = 0;
+#pragma unroll
+      for (int f = 0; f < S_WORDS; ++f) miss |= pat[f] & ~v[f];
+      a.out[i] = miss == 0 ? 1 : 0;
+    }
   }
 }
 

@@ -44,7 +44,15 @@ inline int csbf_part_index(int word_bits, int s, int z, int kidx) {
   return (((word_bits == 64 ? 1 : 0) * kLog2Max + ilog2(s)) * kLog2Max + ilog2(z)) * kNumK + kidx;
 }
 
+// Chained pattern hashing: (op, word bits, s, k).
+constexpr int kChainedSize = 2 * 2 * kLog2Max * kNumK;
+
+inline int chained_index(int op, int word_bits, int s, int kidx) {
+  return ((op * 2 + (word_bits == 64 ? 1 : 0)) * kLog2Max + ilog2(s)) * kNumK + kidx;
+}
+
 struct VariantRegistry {
+  const void* chained[kChainedSize];
   const void* classic[kClassicSize];
   const void* csbf[kCsbfSize];
   const void* csbf_part1[kCsbfPartSize];
@@ -56,6 +64,7 @@ VariantRegistry& variant_registry();
 void ensure_variant_registry();
 
 void register_classic(VariantRegistry&);
+void register_chained(VariantRegistry&);
 void register_csbf_u32_s1(VariantRegistry&);
 void register_csbf_u32_s2(VariantRegistry&);
 void register_csbf_u32_s4(VariantRegistry&);

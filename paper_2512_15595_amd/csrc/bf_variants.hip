@@ -1,5 +1,5 @@
-// bf_variants.hip -- the C ABI of include/bf_variants.h (classic and
-// cache-sectorized layouts) and their mapping selection and launch, reached
+// bf_variants.hip -- the C ABI of include/bf_variants.h (classic,
+// cache-sectorized and chained-hash layouts) and their mapping selection and launch, reached
 // from bf_add / bf_contains / bf_info / bf_set_mapping of bf_api.hip.
 #include <hip/hip_runtime.h>
 
@@ -57,6 +57,7 @@ void ensure_variant_registry() {
   std::call_once(g_variant_once, [] {
     VariantRegistry& r = variant_registry();
     register_classic(r);
+    register_chained(r);
     register_csbf_u32_s1(r);
     register_csbf_u32_s2(r);
     register_csbf_u32_s4(r);
@@ -101,6 +102,12 @@ bf_mapping_t default_variant_mapping(const bf_filter* f, int op) {
     m.keys_per_lane = op == BF_OP_ADD ? 1 : 2;
     return m;
   }
+  if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) {
+    m.lanes_per_key = 1;
+    m.words_per_lane = f->s;
+    m.keys_per_lane = 1;
+    return m;
+  }
   const uint32_t z = f->groups;
   const bool hbm = f->nbytes > (256ull << 20);
   const uint32_t block_bytes = f->s * f->word_bits / 8;
@@ -138,6 +145,10 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
       m.words_per_lane = f->s;
       m.keys_per_lane = 1;
     }
+  } else if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) {
+    m.lanes_per_key = 1;
+    m.words_per_lane = f->s;
+    m.keys_per_lane = 1;
   } else {
     m.lanes_per_key = 1;
     m.words_per_lane = 1;
@@ -147,18 +158,24 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
   // classic adds are always direct; lookups have no strategy
   if (op == BF_OP_CONTAINS)
     m.strategy = BF_STRATEGY_AUTO;
-  else if (f->layout == BF_LAYOUT_CLASSIC)
+  else if (f->layout != BF_LAYOUT_CACHE_SECTORIZED)
     m.strategy = BF_STRATEGY_DIRECT;
   return m;
 }
 
 bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
   if (m.strategy > BF_STRATEGY_PARTITIONED) return BF_EINVAL;
-  if (f->layout == BF_LAYOUT_CLASSIC && m.strategy == BF_STRATEGY_PARTITIONED)
+  if (f->layout != BF_LAYOUT_CACHE_SECTORIZED && m.strategy == BF_STRATEGY_PARTITIONED)
     return BF_EUNSUPPORTED;
   if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
   if (!(m.atomic_bits == 0 || (op == BF_OP_ADD && m.atomic_bits == 32))) return BF_EINVAL;
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) return BF_OK;
+  if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) {
+    if (m.lanes_per_key != 1 || (m.words_per_lane != 0 && m.words_per_lane != f->s) ||
+        m.keys_per_lane > 1)
+      return BF_EINVAL;
+    return BF_OK;
+  }
   if (f->layout == BF_LAYOUT_CLASSIC) {
     if (m.lanes_per_key != 1 || m.words_per_lane > 1) return BF_EINVAL;
     if (!(m.keys_per_lane == 1 || m.keys_per_lane == 2 || m.keys_per_lane == 4)) return BF_EINVAL;
@@ -191,7 +208,25 @@ bf_status variant_launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n,
   if (m.max_workgroups != 0 && grid > m.max_workgroups) grid = m.max_workgroups;
 
   hipError_t e;
-  if (f->layout == BF_LAYOUT_CLASSIC) {
+  if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) {
+    const void* fn = variant_registry().chained[chained_index(
+        op, static_cast<int>(f->word_bits), static_cast<int>(f->s), kidx)];
+    if (fn == nullptr) return BF_EUNSUPPORTED;
+    BfArgs a{};
+    a.words = f->d_words;
+    a.keys = keys;
+    a.out = out;
+    a.n = n;
+    a.hash_init = xxh64_u64_init(f->seed);
+    a.nb_lo = static_cast<uint32_t>(f->num_blocks);
+    a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
+    a.k = f->k;
+    uint64_t g = (n + kBlockThreads - 1) / kBlockThreads;
+    if (g > hard_cap) g = hard_cap;
+    if (m.max_workgroups != 0 && g > m.max_workgroups) g = m.max_workgroups;
+    void* args[] = {&a};
+    e = hipLaunchKernel(fn, dim3(static_cast<uint32_t>(g)), dim3(kBlockThreads), args, 0, stream);
+  } else if (f->layout == BF_LAYOUT_CLASSIC) {
     const int pow2 = pow2_u64(f->num_bits) ? 1 : 0;
     const void* fn = variant_registry().classic[classic_index(op, kidx, static_cast<int>(kt), pow2)];
     if (fn == nullptr) return BF_EUNSUPPORTED;
@@ -249,6 +284,29 @@ bf_status bf_create_classic(uint64_t num_bits, uint32_t k, uint64_t seed, bf_fil
   f->k = k;
   f->seed = seed;
   f->nbytes = num_bits / 8;
+  const bf_status st = alloc_filter_words(f);
+  if (st != BF_OK) return st;
+  *out = f;
+  return BF_OK;
+}
+
+bf_status bf_create_chained(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits,
+                            uint32_t k, uint64_t seed, bf_filter** out) {
+  if (out == nullptr) return BF_EINVAL;
+  const uint32_t s = words_per_block;
+  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
+  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
+  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
+  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
+  bf_filter* f = new (std::nothrow) bf_filter{};
+  if (f == nullptr) return BF_ENOMEM;
+  f->layout = BF_LAYOUT_SECTORIZED_CHAINED;
+  f->num_blocks = num_blocks;
+  f->s = s;
+  f->word_bits = word_bits;
+  f->k = k;
+  f->seed = seed;
+  f->nbytes = num_blocks * s * (word_bits / 8);
   const bf_status st = alloc_filter_words(f);
   if (st != BF_OK) return st;
   *out = f;

@@ -32,7 +32,8 @@ def test_headers_declare_the_boundary():
     names = set()
     for h in HEADERS:
         names |= set(_declared_functions(h))
-    for required in ("bf_create", "bf_create_classic", "bf_create_csbf", "bf_destroy", "bf_add",
+    for required in ("bf_create", "bf_create_classic", "bf_create_csbf", "bf_create_chained",
+                     "bf_destroy", "bf_add",
                      "bf_contains", "bf_clear", "bf_info",
                      "bf_set_mapping", "bf_strerror", "bfb_random_read", "bfb_random_atomic_or",
                      "bfb_gups", "bfb_copy"):
@@ -101,6 +102,11 @@ def test_variant_layouts_validate_without_gpu():
         (4096, 6, 32, 2, 4, 0),     # words per block
     ]:
         st, h = bf.bf_create_csbf(*args)
+        assert st == bf.BF_EINVAL, args
+        assert not h.value
+    for args in [(0, 8, 32, 8, 0), (4096, 3, 32, 8, 0), (4096, 8, 16, 8, 0), (4096, 8, 32, 7, 0),
+                 (4096, 8, 32, 33, 0), (2**32 + 1, 1, 32, 8, 0)]:
+        st, h = bf.bf_create_chained(*args)
         assert st == bf.BF_EINVAL, args
         assert not h.value
 

@@ -340,3 +340,49 @@ def test_csbf_cache_regime_full_size_sampled(s, S, z, k):
     ref.bytes = state
     pick = g.integers(0, queries.size, size=1 << 16)
     assert np.array_equal(out[pick], ref.contains(queries[pick]))
+
+
+# --------------------------------------------------------------------------
+# Chained pattern hashing (the prior-art baseline of the breakdown)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("s,S", [(s, S) for S in (32, 64) for s in (1, 2, 4, 8, 16)])
+def test_chained_bit_exact(s, S):
+    bf = _bf()
+    g = workloads.rng(500 + s + S)
+    for k in sorted({s, 8 if s <= 8 else 16, 16, 11 if s <= 11 else 20}):
+        params = dict(num_blocks=1019, words_per_block=s, word_bits=S, k=k,
+                      seed=int(g.integers(0, 2**63)))
+        adds = g.integers(0, 2**64, size=3 * 256 + 17, dtype=np.uint64)
+        queries = np.concatenate([adds[::2], g.integers(0, 2**64, size=2000, dtype=np.uint64)])
+        ref = oracle.ChainedOracle(**params)
+        ref.add(adds)
+        log(f"chained s={s} S={S} k={k}")
+        f = bf.ChainedHashFilter(**params)
+        try:
+            words, out = _run(f, adds, queries, add_offset=1)
+            info = f.info()
+        finally:
+            f.close()
+        assert info.layout == bf.BF_LAYOUT_SECTORIZED_CHAINED
+        assert np.array_equal(words, ref.bytes), k
+        assert np.array_equal(out, ref.contains(queries)), k
+
+
+def test_chained_mapping_and_strategy_limits():
+    bf = _bf()
+    f = bf.ChainedHashFilter(256, 8, 32, 8, 1)
+    try:
+        f.set_mapping(bf.BF_OP_ADD, 1, 8, 1)
+        with pytest.raises(bf.BfError):
+            f.set_mapping(bf.BF_OP_ADD, 2, 4, 1)
+        with pytest.raises(bf.BfError) as e:
+            f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        assert e.value.status == bf.BF_EUNSUPPORTED
+        big = _keys(1 << 22, 91)                      # dense: would be partitioned if allowed
+        ref = oracle.ChainedOracle(256, 8, 32, 8, 1)
+        ref.add(big[:20000])
+        words, _ = _run(f, big[:20000], np.zeros(0, dtype=np.uint64))
+        assert np.array_equal(words, ref.bytes)
+    finally:
+        f.close()
