@@ -68,7 +68,7 @@ def log(msg: str) -> None:
 def sweep_layout(torch, s: int, word_bits: int, k: int, filter_bytes: int, n_keys: int,
                  reps: int, ops=("add", "contains"), grid_caps=(0,), d_keys=None, d_q=None):
     from . import workloads
-    from .bf import BF_OP_ADD, BF_OP_CONTAINS, BloomFilter
+    from .bf import BF_OP_ADD, BF_OP_CONTAINS, BF_STRATEGY_DIRECT, BloomFilter
 
     block_bytes = s * word_bits // 8
     num_blocks = filter_bytes // block_bytes
@@ -88,7 +88,9 @@ def sweep_layout(torch, s: int, word_bits: int, k: int, filter_bytes: int, n_key
         for op in ops:
             opcode = BF_OP_ADD if op == "add" else BF_OP_CONTAINS
             for m in mappings(s, word_bits, op, grid_caps):
-                f.set_mapping(opcode, *m)
+                # the table holds the direct path's mappings (a dense add would
+                # otherwise take the partitioned strategy, where they do not apply)
+                f.set_mapping(opcode, *m, strategy=BF_STRATEGY_DIRECT if op == "add" else 0)
                 best = None
                 for _ in range(reps + 1):  # first run is a warm-up
                     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
