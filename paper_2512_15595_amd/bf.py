@@ -327,6 +327,7 @@ class _Filter:
         _check(st, what)
         self._h = h
         info = self.info()
+        self.device = int(info.device)
         self.layout = int(info.layout)
         self.k = int(info.k)
         self._nbytes = int(info.size_bytes)
@@ -387,7 +388,7 @@ class _Filter:
         """A device copy of the words as a torch uint8 tensor."""
         import torch
 
-        out = torch.empty(self.size_bytes(), dtype=torch.uint8, device="cuda")
+        out = torch.empty(self.size_bytes(), dtype=torch.uint8, device=f"cuda:{self.device}")
         _check(bf_export_words(self._h, out.data_ptr(), out.numel(), _stream_ptr(stream)),
                "bf_export_words")
         return out
