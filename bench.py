@@ -791,6 +791,40 @@ def run_layouts(args) -> dict:
     }
 
 
+def run_bounds(args) -> dict:
+    """The random-access microbenchmarks versus footprint (1 MiB .. 4 GiB):
+    random aligned 8-byte and 32-byte reads (one and two lanes per segment),
+    32-byte reads through an 8 B/access streamed index, GUPS-style 8-byte
+    read-modify-writes and random atomic ORs, 2^26 accesses each."""
+    import torch
+
+    rows = []
+    for lg in args.bounds_log2_bytes:
+        b = measure_bounds(torch, 1 << lg, 32, 1 << 26)
+        rows.append({"footprint_bytes": 1 << lg, **b["rates_g_per_s"],
+                     "contains_bound": round(b["contains_bound"], 3),
+                     "add_bound": round(b["add_bound"], 3)})
+        log(f"[bounds] 2^{lg} B: read 32 B {b['rates_g_per_s']['read_32B_x1']:.1f}, "
+            f"indexed {b['rates_g_per_s']['read_32B_indexed']:.1f}, "
+            f"atomic {b['rates_g_per_s']['atomic_or_8B_x1']:.1f} G/s")
+    return {
+        "metric": "G random accesses/s vs footprint",
+        "value": rows[-1]["contains_bound"],
+        "unit": "G accesses/s",
+        "n_gpus": 1,
+        "steps": 3,
+        "warmup": 0,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "random_access_bounds_1MiB_4GiB", "accesses": 1 << 26,
+                   "value_is": "largest footprint's contains bound"},
+        "rows": rows,
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--serve-filters", type=int, default=64)
@@ -800,8 +834,10 @@ def main() -> int:
     ap.add_argument("--serve-inflight", type=int, default=16)
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-coalesce-keys", type=int, default=65536)
-    ap.add_argument("--workload", choices=["dram", "batched", "serve", "cache", "breakdown", "layouts"],
+    ap.add_argument("--workload",
+                    choices=["dram", "batched", "serve", "cache", "breakdown", "layouts", "bounds"],
                     default="dram")
+    ap.add_argument("--bounds-log2-bytes", type=int, nargs="+", default=[20, 22, 24, 26, 28, 30, 32])
     ap.add_argument("--layouts-keys", type=int, default=10**9)
     ap.add_argument("--breakdown-log2-keys", type=int, default=26)
     ap.add_argument("--cache-log2-keys", type=int, default=26)
@@ -855,6 +891,9 @@ def main() -> int:
         return 0
     if args.workload == "layouts":
         print(json.dumps(run_layouts(args)), flush=True)
+        return 0
+    if args.workload == "bounds":
+        print(json.dumps(run_bounds(args)), flush=True)
         return 0
     n = 1 << args.log2_keys
     s, S, k = args.words_per_block, args.word_bits, args.k
