@@ -78,12 +78,14 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *   strategy        add only: BF_STRATEGY_*.  The partitioned strategy
  *                   radix-partitions the keys by 64 KiB filter chunk and
  *                   updates each chunk in LDS, so a bulk add performs no
- *                   global atomics; it uses a workspace of 16 bytes per key
- *                   (allocated by the filter on first need, which
- *                   synchronizes the device), and while it runs it owns the
- *                   filter: another add on a different stream must be
- *                   ordered against it (events).  Mapping fields other than
- *                   strategy do not apply to it.  Results are identical. */
+ *                   global atomics; it takes a workspace of ~17 bytes per key
+ *                   from a per-device stream-ordered memory pool and returns
+ *                   it at its end on the same stream (no device
+ *                   synchronization; the pool keeps its peak size reserved
+ *                   for later adds), and while it runs it owns the filter:
+ *                   another add on a different stream must be ordered
+ *                   against it (events).  Mapping fields other than strategy
+ *                   do not apply to it.  Results are identical. */
 typedef struct {
   uint32_t lanes_per_key;
   uint32_t words_per_lane;

@@ -39,7 +39,8 @@ extern "C" {
 typedef struct bf_server bf_server;
 
 typedef struct {
-  uint64_t hbm_budget_bytes;      /* payload bytes allowed in flight (>= the largest request) */
+  uint64_t hbm_budget_bytes;      /* device bytes allowed in flight: keys, results and the
+                                     workspace of partitioned adds (>= the largest request) */
   uint32_t max_inflight;          /* launches in flight at most (>= 1) */
   uint32_t nstreams;              /* device streams used (1..64) */
   uint64_t coalesce_max_keys;     /* requests of at most this many keys may share a launch (0: never) */

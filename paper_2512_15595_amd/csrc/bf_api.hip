@@ -252,7 +252,6 @@ bf_status bf_destroy(bf_filter* f) {
   bf_status st = BF_OK;
   if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
   if (hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
-  if (f->scratch != nullptr && hipFree(f->scratch) != hipSuccess) st = BF_EDEVICE;
   delete f;
   return st;
 }

@@ -17,8 +17,6 @@ struct bf_filter {
   uint64_t nbytes;
   void* d_words;
   bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
-  void* scratch;            // partitioned-construction workspace (grow-only)
-  uint64_t scratch_bytes;
   uint32_t layout;          // BF_LAYOUT_*
   uint32_t groups;          // cache-sectorized z, else 0
   uint64_t num_bits;        // nbytes * 8
@@ -36,6 +34,9 @@ struct PartKernels {
   const void* apply;
 };
 bool partition_applicable(const bf_filter* f, uint64_t n);
+// Workspace bytes a partitioned add of n keys takes from the device pool (0
+// if the filter cannot be partitioned).
+uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n);
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream);
 uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits);
 bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L);

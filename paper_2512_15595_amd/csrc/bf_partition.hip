@@ -5,6 +5,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdint>
+#include <map>
+#include <mutex>
 
 #include "bf_internal.hpp"
 #include "bf_variant_registry.hpp"
@@ -141,28 +144,64 @@ bool partition_applicable(const bf_filter* f, uint64_t n) {
   return n > 0 && n < (1ull << 40) && part_geometry(chunks, shift, 1, a, L);
 }
 
+namespace {
+
+// The construction workspace comes from one stream-ordered memory pool per
+// device: taken at the start of a partitioned add and returned at its end
+// on the same stream, so an add never synchronizes the device and no filter
+// keeps a workspace.  The pool keeps its peak size reserved (release
+// threshold: never), so steady use does not remap memory.
+std::mutex g_pool_mu;
+std::map<int, hipMemPool_t> g_pools;
+
+hipMemPool_t workspace_pool(int device) {
+  std::lock_guard<std::mutex> lk(g_pool_mu);
+  auto it = g_pools.find(device);
+  if (it != g_pools.end()) return it->second;
+  hipMemPoolProps props{};
+  props.allocType = hipMemAllocationTypePinned;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = device;
+  hipMemPool_t pool = nullptr;
+  if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  uint64_t keep = UINT64_MAX;
+  (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+  g_pools[device] = pool;
+  return pool;
+}
+
+bool single_geometry(const bf_filter* f, uint64_t n, PartArgs& a, PartLayout& L) {
+  const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
+  const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
+  return part_geometry(chunks, shift, n, a, L);
+}
+
+}  // namespace
+
+uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n) {
+  PartArgs a{};
+  PartLayout L{};
+  if (!partition_applicable(f, n) || !single_geometry(f, n, a, L)) return 0;
+  return L.total;
+}
+
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
   PartArgs a{};
   PartLayout L{};
-  const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
-  const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
-  if (!part_geometry(chunks, shift, n, a, L)) return BF_EUNSUPPORTED;
+  if (!single_geometry(f, n, a, L)) return BF_EUNSUPPORTED;
   const PartKernels k = part_kernels(f);
   if (k.scatter1 == nullptr) return BF_EUNSUPPORTED;
-  if (f->scratch_bytes < L.total) {
-    if (f->scratch != nullptr) {
-      if (hipFree(f->scratch) != hipSuccess) return BF_EDEVICE;
-      f->scratch = nullptr;
-      f->scratch_bytes = 0;
-    }
-    if (hipMalloc(&f->scratch, L.total) != hipSuccess) {
-      (void)hipGetLastError();
-      f->scratch = nullptr;
-      return BF_ENOMEM;
-    }
-    f->scratch_bytes = L.total;
+  hipMemPool_t pool = workspace_pool(f->device);
+  if (pool == nullptr) return BF_EDEVICE;
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, L.total, pool, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return BF_ENOMEM;
   }
-  part_bind(a, L, f->scratch);
+  part_bind(a, L, ws);
   a.words = f->d_words;
   a.num_blocks = f->num_blocks;
   a.hash_init = xxh64_u64_init(f->seed);
@@ -172,7 +211,9 @@ bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStr
   // the cache-sectorized rule takes the bits per selected word
   a.k = f->layout == BF_LAYOUT_CACHE_SECTORIZED ? f->k / f->groups : f->k;
   a.keys = keys;
-  return part_launch(a, L, k, stream);
+  bf_status st = part_launch(a, L, k, stream);
+  if (hipFreeAsync(ws, stream) != hipSuccess && st == BF_OK) st = BF_EDEVICE;
+  return st;
 }
 
 }  // namespace bfhip

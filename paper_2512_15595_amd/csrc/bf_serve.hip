@@ -60,8 +60,14 @@ struct StreamCtx {
   bool staged_valid = false;
 };
 
-uint64_t payload_bytes(const bf_request_t& r) {
-  return r.n * (r.op == BF_OP_CONTAINS ? 9ull : 8ull);
+// Device bytes a request holds while in flight: its keys and results and,
+// for an add that will take the partitioned construction, the workspace it
+// takes from the device pool.
+uint64_t payload_bytes(const bf_filter* f, const bf_request_t& r) {
+  if (r.op == BF_OP_CONTAINS) return r.n * 9ull;
+  uint64_t bytes = r.n * 8ull;
+  if (use_partitioned(f, r.n, f->mapping[BF_OP_ADD])) bytes += partition_workspace_bytes(f, r.n);
+  return bytes;
 }
 
 }  // namespace
@@ -359,7 +365,7 @@ uint64_t submit_at(bf_server* s, const bf_request_t& r, uint64_t arrival) {
   const uint64_t id = s->submitted++;
   s->results.resize(s->submitted);
   s->results[id] = bf_request_result_t{arrival, 0, 0, 0xffffffffu, BF_OK};
-  s->inbox.push_back(Pending{id, r, arrival, payload_bytes(r)});
+  s->inbox.push_back(Pending{id, r, arrival, payload_bytes(s->filters[r.filter], r)});
   s->stats.requests += 1;
   s->cv_inbox.notify_one();
   return id;
