@@ -6,9 +6,11 @@
  * bf_set_mapping[_ex], bf_destroy), with the same conventions for pointers,
  * streams, errors and concurrency.  They are not accepted by batched plans
  * (bf_batch.h) or servers (bf_serve.h), which give BF_EUNSUPPORTED.  Adds
- * to a cache-sectorized filter choose between the direct and the
- * partitioned strategy as bf.h describes; classic and chained-hash adds are
- * always direct (BF_STRATEGY_PARTITIONED gives BF_EUNSUPPORTED).
+ * to a cache-sectorized filter, and to a classic filter with k in
+ * {4, 6, 8, 12, 16} and at most 2^37 bits (each key then counts as k
+ * records), choose between the direct and the partitioned strategy as bf.h
+ * describes; other classic and all chained-hash adds are direct
+ * (BF_STRATEGY_PARTITIONED gives BF_EUNSUPPORTED).
  *
  * Every layout takes the per-key base hash h = xxHash64 of the key's 8
  * little-endian bytes with the filter seed (paper Sec. IV-B).

@@ -100,6 +100,13 @@ void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
 }
 
 PartKernels part_kernels(const bf_filter* f) {
+  if (f->layout == BF_LAYOUT_CLASSIC) {
+    ensure_variant_registry();
+    const VariantRegistry& r = variant_registry();
+    const bool pow2 = (f->num_bits & (f->num_bits - 1)) == 0;
+    return PartKernels{r.classic_part1[k_index(f->k) * 2 + (pow2 ? 1 : 0)], r.classic_part2,
+                       r.classic_apply};
+  }
   if (f->layout == BF_LAYOUT_CACHE_SECTORIZED) {
     ensure_variant_registry();
     const VariantRegistry& r = variant_registry();
@@ -135,13 +142,39 @@ dim3 part_grid3(const PartArgs& a) {
   return dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>(items, 65535))));
 }
 
-bool partition_applicable(const bf_filter* f, uint64_t n) {
-  if (f->layout != BF_LAYOUT_SECTORIZED && f->layout != BF_LAYOUT_CACHE_SECTORIZED) return false;
-  PartArgs a{};
-  PartLayout L{};
+namespace {
+
+// The classic filter is partitioned as blocks of one 32-bit word, with k
+// records per key; its first pass counts keys (a.n, a.range1) in whole steps
+// of kPartThreads * (kPartPer / k) keys.
+bool single_geometry(const bf_filter* f, uint64_t n, PartArgs& a, PartLayout& L) {
+  if (f->layout == BF_LAYOUT_CLASSIC) {
+    const uint32_t shift = part_chunk_shift(1, 32);
+    const uint64_t words = f->num_bits / 32;
+    const uint64_t chunks = (words + (1ull << shift) - 1) >> shift;
+    if (!part_geometry(chunks, shift, n * f->k, a, L)) return false;
+    const uint64_t step = static_cast<uint64_t>(kPartThreads) * (kPartPer / f->k);
+    const uint64_t range = (n + 1023) / 1024;
+    a.n = n;
+    a.range1 = std::max<uint64_t>((range + step - 1) / step * step, step);
+    return true;
+  }
   const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
   const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
-  return n > 0 && n < (1ull << 40) && part_geometry(chunks, shift, 1, a, L);
+  return part_geometry(chunks, shift, n, a, L);
+}
+
+}  // namespace
+
+bool partition_applicable(const bf_filter* f, uint64_t n) {
+  if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) return false;
+  // classic records address 32-bit words by a 32-bit index (m <= 2^37) and
+  // need a compiled k (at most 16 positions per key)
+  if (f->layout == BF_LAYOUT_CLASSIC && (f->num_bits > (1ull << 37) || k_index(f->k) == 0))
+    return false;
+  PartArgs a{};
+  PartLayout L{};
+  return n > 0 && n < (1ull << 40) && single_geometry(f, 1, a, L);
 }
 
 namespace {
@@ -173,22 +206,11 @@ hipMemPool_t workspace_pool(int device) {
   return pool;
 }
 
-bool single_geometry(const bf_filter* f, uint64_t n, PartArgs& a, PartLayout& L) {
-  const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
-  const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
-  return part_geometry(chunks, shift, n, a, L);
-}
-
 }  // namespace
 
-uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n) {
-  PartArgs a{};
-  PartLayout L{};
-  if (!partition_applicable(f, n) || !single_geometry(f, n, a, L)) return 0;
-  return L.total;
-}
+namespace {
 
-bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
+bf_status partitioned_pass(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
   PartArgs a{};
   PartLayout L{};
   if (!single_geometry(f, n, a, L)) return BF_EUNSUPPORTED;
@@ -203,7 +225,13 @@ bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStr
   }
   part_bind(a, L, ws);
   a.words = f->d_words;
-  a.num_blocks = f->num_blocks;
+  a.num_blocks = f->layout == BF_LAYOUT_CLASSIC ? f->num_bits / 32 : f->num_blocks;
+  a.num_bits = f->num_bits;
+  if ((f->num_bits & (f->num_bits - 1)) == 0) {
+    uint32_t lg = 0;
+    while ((1ull << lg) < f->num_bits) ++lg;
+    a.bit_shift = 64 - lg;
+  }
   a.hash_init = xxh64_u64_init(f->seed);
   a.nb_lo = static_cast<uint32_t>(f->num_blocks);
   a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
@@ -214,6 +242,29 @@ bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStr
   bf_status st = part_launch(a, L, k, stream);
   if (hipFreeAsync(ws, stream) != hipSuccess && st == BF_OK) st = BF_EDEVICE;
   return st;
+}
+
+}  // namespace
+
+// Passes of at most 2^28 records keep the workspace under ~4.6 GB; each pass
+// after the first reads and writes the touched chunks once more.
+bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
+  const uint64_t per_key = f->layout == BF_LAYOUT_CLASSIC ? f->k : 1;
+  const uint64_t max_keys = std::max<uint64_t>((1ull << 28) / per_key, 1);
+  for (uint64_t off = 0; off < n; off += max_keys) {
+    const bf_status st = partitioned_pass(f, keys + off, std::min(max_keys, n - off), stream);
+    if (st != BF_OK) return st;
+  }
+  return BF_OK;
+}
+
+uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n) {
+  PartArgs a{};
+  PartLayout L{};
+  const uint64_t per_key = f->layout == BF_LAYOUT_CLASSIC ? f->k : 1;
+  n = std::min(n, std::max<uint64_t>((1ull << 28) / per_key, 1));
+  if (!partition_applicable(f, n) || !single_geometry(f, n, a, L)) return 0;
+  return L.total;
 }
 
 }  // namespace bfhip

@@ -102,6 +102,9 @@ struct PartArgs {
   // without a work list: apply slices per chunk (> 1 for filters of few
   // chunks, so the apply grid still fills the device)
   uint32_t apply_split;
+  // classic filter (Z = -1 rule): m and, for a power-of-two m, 64 - log2(m)
+  uint64_t num_bits;
+  uint32_t bit_shift;
 };
 
 // One unit of work: slice `split` of `nsplit` of bucket `bucket`.
@@ -187,6 +190,21 @@ struct BlockRule<W, S_WORDS, K, 0> {
   }
 };
 
+// Z = -1: the classic filter (Sec. II-A-1) seen as blocks of one 32-bit
+// word; its records are (word << 32 | bit), one per pattern bit, so the
+// rule sets a single bit.
+template <typename W, int S_WORDS, int K>
+struct BlockRule<W, S_WORDS, K, -1> {
+  static_assert(sizeof(W) == 4 && S_WORDS == 1, "classic records address 32-bit words");
+  __device__ __forceinline__ BlockRule() {}
+  __device__ __forceinline__ void add_global(W* words, uint32_t blk, uint32_t bit, uint32_t) const {
+    __hip_atomic_fetch_or(words + blk, W(1) << bit, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __device__ __forceinline__ void add_lds(W* lds, uint32_t lb, uint32_t bit, uint32_t) const {
+    lds_or<W>(&lds[lb], W(1) << bit);
+  }
+};
+
 // Words and local block of a record's global block (direct fallback).
 template <typename W>
 __device__ __forceinline__ W* record_target(const PartArgs& a, uint32_t gblock, uint32_t& local) {
@@ -203,18 +221,19 @@ __device__ __forceinline__ W* record_target(const PartArgs& a, uint32_t gblock, 
 // j * kPartThreads < valid) with digits dg[] are grouped by digit and
 // written, per digit d, to bucket bucket_of(d) at a reserved offset.
 // Records that do not fit their bucket go to `overflow`.
-template <typename DigitOf, typename BucketOf, typename BaseOf, typename CapOf, typename Overflow>
-__device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], const uint32_t (&dg)[kPartPer],
-                                             uint32_t valid, uint32_t ndigits, uint64_t* stage,
-                                             uint32_t* cnt, uint32_t* start, uint64_t* base,
-                                             unsigned long long* fill, uint64_t* buf,
-                                             DigitOf digit_of, BucketOf bucket_of, BaseOf base_of,
-                                             CapOf cap_of, Overflow overflow) {
+// The records taking part are those with valid_of(j) (record j of this
+// thread); `total` is their number over the workgroup.
+template <typename ValidOf, typename DigitOf, typename BucketOf, typename BaseOf, typename CapOf,
+          typename Overflow>
+__device__ __forceinline__ void scatter_step_masked(
+    const uint64_t (&r)[kPartPer], const uint32_t (&dg)[kPartPer], ValidOf valid_of, uint32_t total,
+    uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start, uint64_t* base,
+    unsigned long long* fill, uint64_t* buf, DigitOf digit_of, BucketOf bucket_of, BaseOf base_of,
+    CapOf cap_of, Overflow overflow) {
   uint32_t rank[kPartPer];
 #pragma unroll
   for (int j = 0; j < kPartPer; ++j) {
-    const uint32_t p = threadIdx.x + j * kPartThreads;
-    if (p < valid) rank[j] = atomicAdd(&cnt[dg[j]], 1u);
+    if (valid_of(j)) rank[j] = atomicAdd(&cnt[dg[j]], 1u);
   }
   __syncthreads();
   // reserve each digit's run in its bucket
@@ -242,11 +261,10 @@ __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], cons
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kPartPer; ++j) {
-    const uint32_t p = threadIdx.x + j * kPartThreads;
-    if (p < valid) stage[start[dg[j]] + rank[j]] = r[j];
+    if (valid_of(j)) stage[start[dg[j]] + rank[j]] = r[j];
   }
   __syncthreads();
-  for (uint32_t p = threadIdx.x; p < valid; p += kPartThreads) {
+  for (uint32_t p = threadIdx.x; p < total; p += kPartThreads) {
     const uint64_t v = stage[p];
     const uint32_t d = digit_of(v);
     const uint64_t pos = base[d] + (p - start[d]);
@@ -258,6 +276,19 @@ __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], cons
   __syncthreads();
   for (uint32_t d = threadIdx.x; d < ndigits; d += kPartThreads) cnt[d] = 0;
   __syncthreads();
+}
+
+// The common case: the first `valid` positions p = tid + j * kPartThreads.
+template <typename DigitOf, typename BucketOf, typename BaseOf, typename CapOf, typename Overflow>
+__device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartPer], const uint32_t (&dg)[kPartPer],
+                                             uint32_t valid, uint32_t ndigits, uint64_t* stage,
+                                             uint32_t* cnt, uint32_t* start, uint64_t* base,
+                                             unsigned long long* fill, uint64_t* buf,
+                                             DigitOf digit_of, BucketOf bucket_of, BaseOf base_of,
+                                             CapOf cap_of, Overflow overflow) {
+  scatter_step_masked(
+      r, dg, [valid](int j) { return threadIdx.x + j * kPartThreads < valid; }, valid, ndigits, stage,
+      cnt, start, base, fill, buf, digit_of, bucket_of, base_of, cap_of, overflow);
 }
 
 // First pass: hash keys and group the records by high digit.
@@ -322,6 +353,60 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter1_kernel(PartArgs a)
           uint32_t local;
           W* w = record_target<W>(a, rec_block(v), local);
           rule.add_global(w, local, rec_lo(v), a.k);
+        });
+  }
+}
+
+// First pass of the classic filter: each key gives K records, one per
+// position p (word p / 32, bit p mod 32); a thread hashes kPartPer / K keys
+// per step.  a.n and a.range1 count keys.
+template <int K, bool POW2>
+__global__ __launch_bounds__(kPartThreads) void part_scatter1_classic_kernel(PartArgs a) {
+  constexpr int kKeys = kPartPer / K;  // keys per thread per step
+  constexpr int kRecs = kKeys * K;     // records per thread per step
+  static_assert(kKeys >= 1, "at most kPartPer positions per key");
+  __shared__ __attribute__((aligned(16))) uint64_t stage[kPartStep];
+  __shared__ uint32_t cnt[kMaxDigits];
+  __shared__ uint32_t start[kMaxDigits];
+  __shared__ uint64_t base[kMaxDigits];
+  for (uint32_t d = threadIdx.x; d < a.f1; d += kPartThreads) cnt[d] = 0;
+  __syncthreads();
+  const BlockRule<uint32_t, 1, K, -1> rule;
+  const uint32_t shift = a.chunk_shift + a.low_bits;
+  constexpr uint64_t kStepKeys = static_cast<uint64_t>(kPartThreads) * kKeys;
+  const uint64_t begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
+  const uint64_t end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
+  for (uint64_t s = begin; s < end; s += kStepKeys) {
+    const uint32_t vkeys = static_cast<uint32_t>(end - s < kStepKeys ? end - s : kStepKeys);
+    bool ok[kKeys];
+    uint64_t r[kPartPer];
+    uint32_t dg[kPartPer];
+#pragma unroll
+    for (int u = 0; u < kKeys; ++u) {
+      const uint32_t idx = threadIdx.x + u * kPartThreads;
+      ok[u] = idx < vkeys;
+      const uint64_t key = ok[u] ? a.keys[s + idx] : 0;
+      const uint64_t h = xxh64_u64(key, a.hash_init);
+#pragma unroll
+      for (int j = 0; j < K; ++j) {
+        const uint64_t p = classic_position<POW2>(h, kSalts64.a[j], a.num_bits, a.bit_shift);
+        const uint32_t word = static_cast<uint32_t>(p >> 5);
+        r[u * K + j] = (static_cast<uint64_t>(word) << 32) | (static_cast<uint32_t>(p) & 31u);
+        dg[u * K + j] = word >> shift;
+      }
+    }
+#pragma unroll
+    for (int j = kRecs; j < kPartPer; ++j) {
+      r[j] = 0;
+      dg[j] = 0;
+    }
+    scatter_step_masked(
+        r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, vkeys * K, a.f1, stage, cnt, start, base,
+        a.fill1, a.buf1, [shift](uint64_t v) { return rec_block(v) >> shift; },
+        [](uint32_t d) { return d; }, [&a](uint32_t d) { return bucket1_base(a, d); },
+        [&a](uint32_t d) { return bucket1_cap(a, d); },
+        [&](uint64_t v) {
+          rule.add_global(static_cast<uint32_t*>(a.words), rec_block(v), rec_lo(v), 0);
         });
   }
 }

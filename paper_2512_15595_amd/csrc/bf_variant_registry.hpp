@@ -55,6 +55,9 @@ struct VariantRegistry {
   const void* chained[kChainedSize];
   const void* classic[kClassicSize];
   const void* csbf[kCsbfSize];
+  const void* classic_part1[kNumK * 2];  // (k, power-of-two m)
+  const void* classic_part2;
+  const void* classic_apply;
   const void* csbf_part1[kCsbfPartSize];
   const void* csbf_part2[kCsbfPartSize];
   const void* csbf_apply[kCsbfPartSize];

@@ -10,6 +10,7 @@
 #include "../../include/bf_variants.h"
 #include "bf_hash.hpp"
 #include "bf_internal.hpp"
+#include "bf_partition.hpp"
 #include "bf_variant_kernels.hpp"
 #include "bf_variant_registry.hpp"
 
@@ -41,10 +42,18 @@ void register_classic_kt(VariantRegistry& r) {
   register_classic_one<K, 1>(r);
   register_classic_one<K, 2>(r);
   register_classic_one<K, 4>(r);
+  if constexpr (K != 0) {
+    r.classic_part1[k_index(K) * 2 + 0] =
+        reinterpret_cast<const void*>(&part_scatter1_classic_kernel<K, false>);
+    r.classic_part1[k_index(K) * 2 + 1] =
+        reinterpret_cast<const void*>(&part_scatter1_classic_kernel<K, true>);
+  }
 }
 }  // namespace
 
 void register_classic(VariantRegistry& r) {
+  r.classic_part2 = reinterpret_cast<const void*>(&part_scatter2_kernel<uint32_t, 1, 0, -1>);
+  r.classic_apply = reinterpret_cast<const void*>(&part_apply_kernel<uint32_t, 1, 0, -1>);
   register_classic_kt<0>(r);
   register_classic_kt<4>(r);
   register_classic_kt<6>(r);
@@ -155,17 +164,17 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
   }
   if (m.keys_per_lane == 0) m.keys_per_lane = 1;
   m.atomic_bits = op == BF_OP_ADD ? 32 : 0;
-  // classic adds are always direct; lookups have no strategy
+  // lookups have no strategy; adds that cannot be partitioned are direct
   if (op == BF_OP_CONTAINS)
     m.strategy = BF_STRATEGY_AUTO;
-  else if (f->layout != BF_LAYOUT_CACHE_SECTORIZED)
+  else if (!partition_applicable(f, 1))
     m.strategy = BF_STRATEGY_DIRECT;
   return m;
 }
 
 bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
   if (m.strategy > BF_STRATEGY_PARTITIONED) return BF_EINVAL;
-  if (f->layout != BF_LAYOUT_CACHE_SECTORIZED && m.strategy == BF_STRATEGY_PARTITIONED)
+  if (m.strategy == BF_STRATEGY_PARTITIONED && !partition_applicable(f, 1))
     return BF_EUNSUPPORTED;
   if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
   if (!(m.atomic_bits == 0 || (op == BF_OP_ADD && m.atomic_bits == 32))) return BF_EINVAL;
@@ -191,8 +200,10 @@ bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_
 bf_status variant_launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                          hipStream_t stream) {
   ensure_variant_registry();
-  if (op == BF_OP_ADD && f->layout == BF_LAYOUT_CACHE_SECTORIZED &&
-      use_partitioned(f, n, f->mapping[BF_OP_ADD]))
+  // a classic key is k records of the partitioned construction
+  const uint64_t records = f->layout == BF_LAYOUT_CLASSIC ? n * f->k : n;
+  if (op == BF_OP_ADD && f->layout != BF_LAYOUT_SECTORIZED_CHAINED &&
+      use_partitioned(f, records, f->mapping[BF_OP_ADD]))
     return partitioned_add(f, keys, n, stream);
   const bf_mapping_t m = variant_resolve_mapping(f, op);
   uint32_t kt = m.keys_per_lane;

@@ -107,14 +107,62 @@ def test_classic_edges():
         assert np.array_equal(f.words().cpu().numpy(), ref.bytes)
         info = f.info()
         assert info.layout == bf.BF_LAYOUT_CLASSIC and info.num_bits == m
-        assert info.size_bytes == m // 8 and info.mapping[bf.BF_OP_ADD].strategy == bf.BF_STRATEGY_DIRECT
+        assert info.size_bytes == m // 8 and info.mapping[bf.BF_OP_ADD].strategy == bf.BF_STRATEGY_AUTO
         with pytest.raises(bf.BfError):
             f.set_mapping(bf.BF_OP_ADD, 2, 1, 1)
-        with pytest.raises(bf.BfError) as e:
-            f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
-        assert e.value.status == bf.BF_EUNSUPPORTED
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
     finally:
         f.close()
+    g = bf.ClassicFilter(m, 5, 3)          # runtime k: no partitioned construction
+    try:
+        assert g.info().mapping[bf.BF_OP_ADD].strategy == bf.BF_STRATEGY_DIRECT
+        with pytest.raises(bf.BfError) as e:
+            g.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        assert e.value.status == bf.BF_EUNSUPPORTED
+    finally:
+        g.close()
+
+
+@pytest.mark.parametrize("m,k", [(1 << 20, 8), (64 * 40_003, 6), (1 << 23, 16), (64 * 7777, 12),
+                                 (1 << 16, 4), (64 * 1000, 16)])
+def test_classic_partitioned_add_bit_exact(m, k):
+    """Forced partitioned construction of the classic filter (k records per
+    key, grouped by 64 KiB chunk); a quarter of the keys repeat one key, so
+    its chunks' buckets overflow into the direct fallback."""
+    bf = _bf()
+    adds = _keys(300_000, m % 1000 + k)
+    adds[: adds.size // 4] = adds[3]
+    ref = oracle.ClassicOracle(m, k, 21)
+    ref.add(adds)
+    queries = np.concatenate([adds[::7], _keys(50_000, 5)])
+    log(f"classic partitioned m={m} k={k}")
+    f = bf.ClassicFilter(m, k, 21)
+    try:
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        words, out = _run(f, adds, queries, add_offset=1)
+    finally:
+        f.close()
+    assert np.array_equal(words, ref.bytes)
+    assert np.array_equal(out, ref.contains(queries))
+
+
+def test_classic_auto_strategy_matches_direct():
+    bf = _bf()
+    m, k = 1 << 28, 8
+    adds = _keys(1 << 21, 44)
+    states = []
+    for strategy in (bf.BF_STRATEGY_AUTO, bf.BF_STRATEGY_DIRECT):
+        f = bf.ClassicFilter(m, k, 9)
+        try:
+            f.set_mapping(bf.BF_OP_ADD, strategy=strategy)
+            f.add(to_device(adds))
+            states.append(f.words().cpu().numpy())
+        finally:
+            f.close()
+    assert np.array_equal(states[0], states[1])
+    sel = np.unique(workloads.rng(45).integers(0, m // 64, size=4096, dtype=np.uint64))
+    want = oracle.classic_words(m, k, 9, adds, sel)
+    assert np.array_equal(states[0].view("<u8")[sel.astype(np.int64)], want)
 
 
 def test_classic_cache_regime_full_size_sampled():
