@@ -556,7 +556,7 @@ def run_breakdown(args) -> dict:
     the paper's parameters, S = 64, k = 16, B = 256 (s = 4), for an
     L2-resident (2 MiB) and an HBM-resident (1 GiB) filter: add then lookup of
     2^log2_keys uniform keys, each step of the sequence measured on its own:
-      1 classic filter of the same size;
+      1 classic filter of the same size, direct (atomic) construction;
       2 sectorized, chained pattern hashing, one lane per key, direct add;
       3 + multiplicative pattern hashing (one lane per key, direct add);
       4 + horizontal add with the hash shared by the group (best THETA in
@@ -602,6 +602,7 @@ def run_breakdown(args) -> dict:
         b = nbytes // (s * S // 8)
         res = {}
         f = bfmod.ClassicFilter(nbytes * 8, k, 3)
+        f.set_mapping(A, strategy=DIRECT)  # the baseline: one atomic per position
         res["1_classic"] = rates(f)
         f.close()
         f = bfmod.ChainedHashFilter(b, s, S, k, 3)
