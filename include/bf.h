@@ -127,7 +127,18 @@ bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block,
                     uint32_t word_bits, uint32_t k, uint64_t seed,
                     bf_filter **out);
 
-/* Frees the words (after a device synchronization) and the handle.
+/* A filter over caller-owned device memory (e.g. a torch tensor): as
+ * bf_create, but the words are d_words (nbytes must equal num_blocks *
+ * words_per_block * word_bits / 8, 256-byte aligned) and are neither zeroed
+ * nor freed by the library; the caller keeps them alive until bf_destroy.
+ * Use it to adopt saved words in place or to place a filter in memory the
+ * caller manages.  Allocates nothing on the device. */
+bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits,
+                       uint32_t k, uint64_t seed, void *d_words, uint64_t nbytes,
+                       bf_filter **out);
+
+/* Frees the words (after a device synchronization; not for bf_create_in
+ * filters, whose words stay the caller's) and the handle.
  * NULL is accepted and ignored. */
 bf_status bf_destroy(bf_filter *f);
 

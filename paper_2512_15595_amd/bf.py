@@ -74,6 +74,8 @@ class bf_info_t(ctypes.Structure):
 _u64, _u32, _i32, _vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_void_p
 _lib.bf_create.argtypes = [_u64, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create.restype = _i32
+_lib.bf_create_in.argtypes = [_u64, _u32, _u32, _u32, _u64, _vp, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create_in.restype = _i32
 _lib.bf_create_classic.argtypes = [_u64, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create_classic.restype = _i32
 _lib.bf_create_csbf.argtypes = [_u64, _u32, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
@@ -203,6 +205,15 @@ def bf_create(num_blocks: int, words_per_block: int, word_bits: int, k: int, see
     h = _vp()
     st = _lib.bf_create(num_blocks, words_per_block, word_bits, k, seed & (2**64 - 1),
                         ctypes.byref(h))
+    return st, h
+
+
+def bf_create_in(num_blocks: int, words_per_block: int, word_bits: int, k: int, seed: int,
+                 d_words: int, nbytes: int):
+    """Returns (status, handle) of a filter over caller-owned device words."""
+    h = _vp()
+    st = _lib.bf_create_in(num_blocks, words_per_block, word_bits, k, seed & (2**64 - 1), d_words,
+                           nbytes, ctypes.byref(h))
     return st, h
 
 
@@ -415,6 +426,24 @@ class BloomFilter(_Filter):
         self.seed = seed
         st, h = bf_create(num_blocks, words_per_block, word_bits, k, seed)
         self._adopt(st, h, "bf_create")
+
+
+class BloomFilterView(_Filter):
+    """Sectorized filter over a caller-owned torch tensor (bf_create_in); the
+    tensor must stay alive while the filter is used and is not zeroed."""
+
+    def __init__(self, words, num_blocks: int, words_per_block: int = 8, word_bits: int = 32,
+                 k: int = 8, seed: int = 0):
+        if not words.is_cuda or not words.is_contiguous():
+            raise ValueError("words must be a contiguous CUDA tensor")
+        self.num_blocks = num_blocks
+        self.words_per_block = words_per_block
+        self.word_bits = word_bits
+        self.seed = seed
+        self._words = words  # keeps the storage alive
+        st, h = bf_create_in(num_blocks, words_per_block, word_bits, k, seed, words.data_ptr(),
+                             words.numel() * words.element_size())
+        self._adopt(st, h, "bf_create_in")
 
 
 class ClassicFilter(_Filter):

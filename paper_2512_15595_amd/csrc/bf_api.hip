@@ -190,6 +190,7 @@ bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
 
 bf_status bfhip::alloc_filter_words(bf_filter* f) {
   f->num_bits = f->nbytes * 8;
+  f->owns_words = true;
   if (hipGetDevice(&f->device) != hipSuccess) {
     delete f;
     return BF_EDEVICE;
@@ -247,11 +248,41 @@ bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word
   return BF_OK;
 }
 
+bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits,
+                       uint32_t k, uint64_t seed, void* d_words, uint64_t nbytes, bf_filter** out) {
+  if (out == nullptr || d_words == nullptr) return BF_EINVAL;
+  const uint32_t s = words_per_block;
+  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
+  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
+  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
+  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
+  if (nbytes != num_blocks * s * (word_bits / 8)) return BF_EINVAL;
+  if (reinterpret_cast<uintptr_t>(d_words) % 256 != 0) return BF_EINVAL;
+  bf_filter* f = new (std::nothrow) bf_filter{};
+  if (f == nullptr) return BF_ENOMEM;
+  f->layout = BF_LAYOUT_SECTORIZED;
+  f->num_blocks = num_blocks;
+  f->s = s;
+  f->word_bits = word_bits;
+  f->k = k;
+  f->seed = seed;
+  f->nbytes = nbytes;
+  f->num_bits = nbytes * 8;
+  f->d_words = d_words;
+  f->owns_words = false;
+  if (hipGetDevice(&f->device) != hipSuccess) {
+    delete f;
+    return BF_EDEVICE;
+  }
+  *out = f;
+  return BF_OK;
+}
+
 bf_status bf_destroy(bf_filter* f) {
   if (f == nullptr) return BF_OK;
   bf_status st = BF_OK;
   if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
-  if (hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
+  if (f->owns_words && hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
   delete f;
   return st;
 }

@@ -18,6 +18,7 @@ struct bf_filter {
   void* d_words;
   bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
   uint32_t layout;          // BF_LAYOUT_*
+  bool owns_words;          // false for bf_create_in
   uint32_t groups;          // cache-sectorized z, else 0
   uint64_t num_bits;        // nbytes * 8
 };

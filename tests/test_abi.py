@@ -32,7 +32,8 @@ def test_headers_declare_the_boundary():
     names = set()
     for h in HEADERS:
         names |= set(_declared_functions(h))
-    for required in ("bf_create", "bf_create_classic", "bf_create_csbf", "bf_create_chained",
+    for required in ("bf_create", "bf_create_in", "bf_create_classic", "bf_create_csbf",
+                     "bf_create_chained",
                      "bf_destroy", "bf_add",
                      "bf_contains", "bf_clear", "bf_info",
                      "bf_set_mapping", "bf_strerror", "bfb_random_read", "bfb_random_atomic_or",
@@ -107,6 +108,23 @@ def test_variant_layouts_validate_without_gpu():
     for args in [(0, 8, 32, 8, 0), (4096, 3, 32, 8, 0), (4096, 8, 16, 8, 0), (4096, 8, 32, 7, 0),
                  (4096, 8, 32, 33, 0), (2**32 + 1, 1, 32, 8, 0)]:
         st, h = bf.bf_create_chained(*args)
+        assert st == bf.BF_EINVAL, args
+        assert not h.value
+
+
+def test_create_in_validates_without_gpu():
+    _ensure_built()
+    from paper_2512_15595_amd import bf
+
+    nb, nbytes = 4096, 4096 * 32
+    for args in [
+        (nb, 8, 32, 8, 0, 0, nbytes),            # null words
+        (nb, 8, 32, 8, 0, 4096, nbytes - 32),    # wrong size
+        (nb, 8, 32, 8, 0, 4096 + 128, nbytes),   # not 256-byte aligned
+        (nb, 8, 32, 7, 0, 4096, nbytes),         # k < s
+        (0, 8, 32, 8, 0, 4096, 0),               # no blocks
+    ]:
+        st, h = bf.bf_create_in(*args)
         assert st == bf.BF_EINVAL, args
         assert not h.value
 

@@ -263,3 +263,33 @@ def test_partitioned_overflow_with_repeated_keys():
         torch.cuda.synchronize()
     finally:
         f.close()
+
+
+def test_filter_over_caller_owned_words():
+    """bf_create_in: the caller's tensor is the filter state (adds land in it,
+    byte-identical to the oracle) and saved words can be adopted in place."""
+    bf = _bf()
+    params = dict(num_blocks=3001, words_per_block=4, word_bits=64, k=8, seed=5)
+    nbytes = params["num_blocks"] * 4 * 8
+    words = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
+    adds = workloads.rng(90).integers(0, 2**64, size=40_000, dtype=np.uint64)
+    queries = np.concatenate([adds[::4], workloads.rng(91).integers(0, 2**64, size=20_000,
+                                                                    dtype=np.uint64)])
+    want_words, want_out = _oracle(params, adds, queries)
+    v = bf.BloomFilterView(words, **params)
+    try:
+        assert v.info().d_words == words.data_ptr()
+        v.add(to_device(adds))
+        out = v.contains(to_device(queries)).cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        v.close()
+    assert np.array_equal(words.cpu().numpy(), want_words)        # the tensor is the state
+    assert np.array_equal(out, want_out)
+    saved = words.clone()
+    w = bf.BloomFilterView(saved, **params)                       # adopt saved words
+    try:
+        assert np.array_equal(w.contains(to_device(queries)).cpu().numpy(), want_out)
+    finally:
+        w.close()
+    assert words.sum().item() > 0                                  # destroy freed nothing
