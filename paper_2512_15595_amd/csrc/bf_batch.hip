@@ -232,9 +232,9 @@ bf_status build_partitioned_graph(bf_batch* b) {
   } steps[] = {
       {reinterpret_cast<const void*>(&part_zero_kernel),
        dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>((nfill + 255) / 256, 4096)))),
-       dim3(kPartThreads), zargs},
-      {b->part_k.scatter1, part_grid1(b->part), dim3(kPartThreads), pargs},
-      {b->part_k.scatter2, part_grid2(b->part), dim3(kPartThreads), pargs},
+       dim3(kZeroThreads), zargs},
+      {b->part_k.scatter1, part_grid1(b->part), dim3(b->part_k.threads1), pargs},
+      {b->part_k.scatter2, part_grid2(b->part), dim3(kScatter2Threads), pargs},
       {b->part_k.apply, part_grid3(b->part), dim3(kApplyThreads), pargs},
   };
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return BF_EDEVICE;

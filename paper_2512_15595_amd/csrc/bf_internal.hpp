@@ -27,12 +27,13 @@ namespace bfhip {
 // Partitioned construction (bf_partition.hip).
 struct PartArgs;
 struct PartLayout {
-  uint64_t off_buf1, off_buf2, off_fill, nfill, total;
+  uint64_t off_buf1, off_buf2, off_fill, nfill1, nfill, total;
 };
 struct PartKernels {
   const void* scatter1;
   const void* scatter2;
   const void* apply;
+  uint32_t threads1;  // workgroup size of scatter1
 };
 bool partition_applicable(const bf_filter* f, uint64_t n);
 // Workspace bytes a partitioned add of n keys takes from the device pool (0
@@ -41,6 +42,10 @@ uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n);
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream);
 uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits);
 bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L);
+// Switches a one-filter geometry to sliced high-digit buckets;
+// records_per_key is 1, or k for the classic filter, whose a.n and a.range1
+// count keys.
+void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key);
 void part_bind(PartArgs& a, const PartLayout& L, void* base);
 PartKernels part_kernels(const bf_filter* f);
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k, hipStream_t stream);

@@ -16,9 +16,9 @@
 
 namespace bfhip {
 
-__global__ __launch_bounds__(kPartThreads) void part_zero_kernel(unsigned long long* p, uint64_t n) {
-  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kPartThreads;
-  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kPartThreads + threadIdx.x; i < n; i += stride)
+__global__ __launch_bounds__(kZeroThreads) void part_zero_kernel(unsigned long long* p, uint64_t n) {
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * kZeroThreads;
+  for (uint64_t i = static_cast<uint64_t>(blockIdx.x) * kZeroThreads + threadIdx.x; i < n; i += stride)
     p[i] = 0;
 }
 
@@ -54,7 +54,7 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
   a.chunks = chunks;
   // digits balanced between the passes: f2 ~ sqrt(chunks)
   const uint64_t root = static_cast<uint64_t>(std::ceil(std::sqrt(static_cast<double>(chunks))));
-  a.f2 = std::min<uint32_t>(ceil_pow2(std::max<uint64_t>(root, 1)), 512);
+  a.f2 = std::min<uint32_t>(ceil_pow2(std::max<uint64_t>(root, 1)), kMaxDigits2);
   a.low_bits = 0;
   while ((1u << a.low_bits) < a.f2) ++a.low_bits;
   const uint64_t f1 = (chunks + a.f2 - 1) / a.f2;
@@ -85,10 +85,32 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
   L.off_buf2 = off;
   off = align256(off + 8ull * chunks * a.cap2);
   L.off_fill = off;
+  L.nfill1 = a.f1;
   L.nfill = a.f1 + chunks;
   off = align256(off + 8ull * L.nfill);
   L.total = off;
   return true;
+}
+
+// Sliced high-digit buckets: pass-1 workgroup w owns slice (d, w) of every
+// high digit d, sized for its expected share range1 * records_per_key / f1.
+// Slices hold the slack (six standard deviations) that a shared bucket needs
+// only once, so the first record buffer takes more address space; traffic
+// is unchanged, as only filled records are written and read.
+void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key) {
+  a.g1 = static_cast<uint32_t>(std::max<uint64_t>((a.n + a.range1 - 1) / a.range1, 1));
+  a.q = std::min<uint32_t>(a.q, a.g1);  // every pass-2 workgroup reads a slice
+  a.cs1 = capacity(static_cast<double>(a.range1 * records_per_key) / a.f1, 16, 16);
+  uint64_t off = 0;
+  L.off_buf1 = off;
+  off = align256(off + 8ull * a.f1 * a.g1 * a.cs1);
+  L.off_buf2 = off;
+  off = align256(off + 8ull * a.chunks * a.cap2);
+  L.off_fill = off;
+  L.nfill1 = static_cast<uint64_t>(a.f1) * a.g1;
+  L.nfill = L.nfill1 + a.chunks;
+  off = align256(off + 8ull * L.nfill);
+  L.total = off;
 }
 
 void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
@@ -96,7 +118,7 @@ void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
   a.buf1 = reinterpret_cast<uint64_t*>(base + L.off_buf1);
   a.buf2 = reinterpret_cast<uint64_t*>(base + L.off_buf2);
   a.fill1 = reinterpret_cast<unsigned long long*>(base + L.off_fill);
-  a.fill2 = a.fill1 + a.f1;
+  a.fill2 = a.fill1 + L.nfill1;
 }
 
 PartKernels part_kernels(const bf_filter* f) {
@@ -105,31 +127,35 @@ PartKernels part_kernels(const bf_filter* f) {
     const VariantRegistry& r = variant_registry();
     const bool pow2 = (f->num_bits & (f->num_bits - 1)) == 0;
     return PartKernels{r.classic_part1[k_index(f->k) * 2 + (pow2 ? 1 : 0)], r.classic_part2,
-                       r.classic_apply};
+                       r.classic_apply, kClassicThreads};
   }
   if (f->layout == BF_LAYOUT_CACHE_SECTORIZED) {
     ensure_variant_registry();
     const VariantRegistry& r = variant_registry();
     const int idx = csbf_part_index(static_cast<int>(f->word_bits), static_cast<int>(f->s),
                                     static_cast<int>(f->groups), k_index(f->k));
-    return PartKernels{r.csbf_part1[idx], r.csbf_part2[idx], r.csbf_apply[idx]};
+    return PartKernels{r.csbf_part1[idx], r.csbf_part2[idx], r.csbf_apply[idx], kScatter1Threads};
   }
   ensure_registry();
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
-  return PartKernels{registry().part1_fn[idx], registry().part2_fn[idx], registry().apply_fn[idx]};
+  return PartKernels{registry().part1_fn[idx], registry().part2_fn[idx], registry().apply_fn[idx],
+                     kScatter1Threads};
 }
 
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k,
                       hipStream_t stream) {
   if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_EUNSUPPORTED;
-  const uint64_t zgrid = std::min<uint64_t>((L.nfill + kPartThreads - 1) / kPartThreads, 4096);
+  // shared buckets' fill counters start at zero; slice counts are written
+  // by their owners
+  const uint64_t zbegin = a.cs1 ? L.nfill1 : 0, zn = L.nfill - zbegin;
+  const uint64_t zgrid = std::min<uint64_t>((zn + kZeroThreads - 1) / kZeroThreads, 4096);
   hipLaunchKernelGGL(part_zero_kernel, dim3(static_cast<uint32_t>(std::max<uint64_t>(zgrid, 1))),
-                     dim3(kPartThreads), 0, stream, a.fill1, L.nfill);
+                     dim3(kZeroThreads), 0, stream, a.fill1 + zbegin, zn);
   PartArgs copy = a;
   void* args[] = {&copy};
-  if (hipLaunchKernel(k.scatter1, part_grid1(a), dim3(kPartThreads), args, 0, stream) != hipSuccess ||
-      hipLaunchKernel(k.scatter2, part_grid2(a), dim3(kPartThreads), args, 0, stream) != hipSuccess ||
+  if (hipLaunchKernel(k.scatter1, part_grid1(a), dim3(k.threads1), args, 0, stream) != hipSuccess ||
+      hipLaunchKernel(k.scatter2, part_grid2(a), dim3(kScatter2Threads), args, 0, stream) != hipSuccess ||
       hipLaunchKernel(k.apply, part_grid3(a), dim3(kApplyThreads), args, 0, stream) != hipSuccess)
     return BF_EDEVICE;
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
@@ -146,22 +172,25 @@ namespace {
 
 // The classic filter is partitioned as blocks of one 32-bit word, with k
 // records per key; its first pass counts keys (a.n, a.range1) in whole steps
-// of kPartThreads * (kPartPer / k) keys.
+// of kClassicThreads * (kPartStep / kClassicThreads / k) keys.
 bool single_geometry(const bf_filter* f, uint64_t n, PartArgs& a, PartLayout& L) {
   if (f->layout == BF_LAYOUT_CLASSIC) {
     const uint32_t shift = part_chunk_shift(1, 32);
     const uint64_t words = f->num_bits / 32;
     const uint64_t chunks = (words + (1ull << shift) - 1) >> shift;
     if (!part_geometry(chunks, shift, n * f->k, a, L)) return false;
-    const uint64_t step = static_cast<uint64_t>(kPartThreads) * (kPartPer / f->k);
+    const uint64_t step = static_cast<uint64_t>(kClassicThreads) * (kPartStep / kClassicThreads / f->k);
     const uint64_t range = (n + 1023) / 1024;
     a.n = n;
     a.range1 = std::max<uint64_t>((range + step - 1) / step * step, step);
+    part_slice(a, L, f->k);
     return true;
   }
   const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
   const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
-  return part_geometry(chunks, shift, n, a, L);
+  if (!part_geometry(chunks, shift, n, a, L)) return false;
+  part_slice(a, L, 1);
+  return true;
 }
 
 }  // namespace
