@@ -78,7 +78,7 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *   strategy        add only: BF_STRATEGY_*.  The partitioned strategy
  *                   radix-partitions the keys by 64 KiB filter chunk and
  *                   updates each chunk in LDS, so a bulk add performs no
- *                   global atomics; it takes a workspace of ~17 bytes per key
+ *                   global atomics; it takes a workspace of 17-21 bytes per key
  *                   from a per-device stream-ordered memory pool and returns
  *                   it at its end on the same stream (no device
  *                   synchronization; the pool keeps its peak size reserved

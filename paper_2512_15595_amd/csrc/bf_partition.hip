@@ -275,7 +275,7 @@ bf_status partitioned_pass(bf_filter* f, const uint64_t* keys, uint64_t n, hipSt
 
 }  // namespace
 
-// Passes of at most 2^28 records keep the workspace under ~4.6 GB; each pass
+// Passes of at most 2^28 records keep the workspace under ~5.5 GB; each pass
 // after the first reads and writes the touched chunks once more.
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
   const uint64_t per_key = f->layout == BF_LAYOUT_CLASSIC ? f->k : 1;
