@@ -45,15 +45,16 @@
 
 namespace bfhip {
 
-constexpr int kPartStep = 4096;                     // records per LDS-staged scatter step
+constexpr int kPartStep = 8192;                     // records per LDS-staged scatter step
 // Workgroup shapes of the scatter passes (threads; each thread holds
 // kPartStep / threads records of a step).  Measured on MI355X, one wide
-// workgroup per CU beats several narrow ones: the first pass runs 16 waves
-// of 4 keys, the second 8 waves of 8 records; the classic first pass keeps
-// 16 records per thread for up to 16 positions per key.
+// workgroup per CU with a long step beats several narrow ones: both passes
+// run 16 waves of 8 records (a step's 64 KiB stage then fills most of the
+// CU's LDS); the classic first pass keeps 16 records per thread for up to
+// 16 positions per key.
 constexpr int kScatter1Threads = 1024;
-constexpr int kScatter2Threads = 512;
-constexpr int kClassicThreads = 256;
+constexpr int kScatter2Threads = 1024;
+constexpr int kClassicThreads = 512;
 constexpr int kZeroThreads = 256;
 constexpr int kApplyThreads = 1024;                 // apply: 16 waves share one chunk
 constexpr int kChunkBytes = 64 * 1024;              // LDS bytes owned per chunk
