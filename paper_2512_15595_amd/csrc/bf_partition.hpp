@@ -164,21 +164,29 @@ __device__ __forceinline__ void lds_or(W* p, W v) {
     atomicOr(reinterpret_cast<unsigned int*>(p), static_cast<unsigned int>(v));
 }
 
-// LDS position of word f of chunk-local block lb: word f ^ (lb mod s) of the
-// block.  Without the swizzle word f of every block falls in the same few
-// banks (its address is f modulo the block size), so one LDS instruction
-// (64 lanes, 64 random blocks, the same f) conflicts on them: measured on
-// MI355X, 16 x 64-bit blocks apply at 27 Gkeys/s unswizzled and 60 swizzled.
-template <int S_WORDS>
+// LDS position of word f (of width 4 * PER bytes) of chunk-local block lb:
+// word f ^ key(lb) of the block.  With 64 four-byte banks, a block of
+// S_WORDS * PER banks starts in one of G = 64 / (S_WORDS * PER) bank groups,
+// chosen by the low log2(G) bits of lb.  One LDS instruction of an apply
+// touches word f of 64 random blocks.  Unswizzled, they all sit in the G
+// banks word f can occupy; keyed by lb mod s, the word within the group is
+// still a function of the same low bits, so they reach only max(G, s) banks
+// (8 for 8 x 32-bit blocks; measured on MI355X: 82 % of LDS-active cycles
+// in bank conflicts).  Keyed by the bits above the group bits,
+// key = (lb >> log2 G) mod s, the group and the word within it are
+// independent and the lanes spread over all banks (also over 32 banks).
+constexpr int log2_floor(int v) { return v > 1 ? 1 + log2_floor(v / 2) : 0; }
+template <int S_WORDS, int PER = 1>
 __device__ __forceinline__ uint32_t lds_word(uint32_t lb, uint32_t f) {
-  return (lb * S_WORDS) | ((f ^ lb) & (S_WORDS - 1));
+  constexpr int kGroups = 64 / (S_WORDS * PER) > 1 ? 64 / (S_WORDS * PER) : 1;
+  constexpr int kShift = log2_floor(kGroups);
+  return (lb * S_WORDS) | ((f ^ (lb >> kShift)) & (S_WORDS - 1));
 }
-
-// The same for a 32-bit index t into the chunk image (W of width 4 * per).
+// The same for a 32-bit index t into the chunk image (W of width 4 * PER).
 template <int S_WORDS, int PER>
 __device__ __forceinline__ uint32_t lds_u32(uint32_t t) {
   const uint32_t e = t / PER;
-  return lds_word<S_WORDS>(e / S_WORDS, e & (S_WORDS - 1)) * PER + t % PER;
+  return lds_word<S_WORDS, PER>(e / S_WORDS, e & (S_WORDS - 1)) * PER + t % PER;
 }
 
 // What a record does to its block, per layout: Z = 0 is the sectorized
@@ -196,7 +204,7 @@ struct BlockRule {
   __device__ __forceinline__ void add_lds(W* lds, uint32_t lb, uint32_t lo, uint32_t k) const {
 #pragma unroll
     for (int i = 0; i < Z; ++i)
-      lds_or<W>(&lds[lds_word<S_WORDS>(lb, ln.word(i, lo))], ln.pattern(i, lo, k));
+      lds_or<W>(&lds[lds_word<S_WORDS, sizeof(W) / 4>(lb, ln.word(i, lo))], ln.pattern(i, lo, k));
   }
 };
 
@@ -211,7 +219,7 @@ struct BlockRule<W, S_WORDS, K, 0> {
 #pragma unroll
     for (int f = 0; f < S_WORDS; ++f) {
       const W pat = lp.word(0, f, lo, k);
-      if (pat) lds_or<W>(&lds[lds_word<S_WORDS>(lb, static_cast<uint32_t>(f))], pat);
+      if (pat) lds_or<W>(&lds[lds_word<S_WORDS, sizeof(W) / 4>(lb, static_cast<uint32_t>(f))], pat);
     }
   }
 };
