@@ -177,10 +177,13 @@ __device__ __forceinline__ void lds_or(W* p, W v) {
 // independent and the lanes spread over all banks (also over 32 banks).
 constexpr int log2_floor(int v) { return v > 1 ? 1 + log2_floor(v / 2) : 0; }
 template <int S_WORDS, int PER = 1>
-__device__ __forceinline__ uint32_t lds_word(uint32_t lb, uint32_t f) {
+__device__ __forceinline__ uint32_t lds_key(uint32_t lb) {
   constexpr int kGroups = 64 / (S_WORDS * PER) > 1 ? 64 / (S_WORDS * PER) : 1;
-  constexpr int kShift = log2_floor(kGroups);
-  return (lb * S_WORDS) | ((f ^ (lb >> kShift)) & (S_WORDS - 1));
+  return (lb >> log2_floor(kGroups)) & (S_WORDS - 1);
+}
+template <int S_WORDS, int PER = 1>
+__device__ __forceinline__ uint32_t lds_word(uint32_t lb, uint32_t f) {
+  return (lb * S_WORDS) | (f ^ lds_key<S_WORDS, PER>(lb));
 }
 // The same for a 32-bit index t into the chunk image (W of width 4 * PER).
 template <int S_WORDS, int PER>
@@ -216,10 +219,23 @@ struct BlockRule<W, S_WORDS, K, 0> {
     add_block<W, S_WORDS, K, 1, S_WORDS, false>(words, blk, lo, lp, k);
   }
   __device__ __forceinline__ void add_lds(W* lds, uint32_t lb, uint32_t lo, uint32_t k) const {
+    if constexpr (sizeof(W) == 4 && S_WORDS >= 2) {
+      // Words f and f + 1 (f even) sit at positions f ^ key and (f ^ key) ^ 1
+      // of the block: one aligned 8-byte pair, so one 64-bit LDS atomic
+      // covers both (their order within it flips with the key's low bit).
+      const uint32_t key = lds_key<S_WORDS, 1>(lb);
 #pragma unroll
-    for (int f = 0; f < S_WORDS; ++f) {
-      const W pat = lp.word(0, f, lo, k);
-      if (pat) lds_or<W>(&lds[lds_word<S_WORDS, sizeof(W) / 4>(lb, static_cast<uint32_t>(f))], pat);
+      for (int f = 0; f < S_WORDS; f += 2) {
+        const uint64_t p0 = lp.word(0, f, lo, k), p1 = lp.word(0, f + 1, lo, k);
+        const uint64_t v = (key & 1u) ? (p0 << 32 | p1) : (p1 << 32 | p0);
+        if (v) lds_or<uint64_t>(reinterpret_cast<uint64_t*>(lds + lb * S_WORDS + ((f ^ key) & ~1u)), v);
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < S_WORDS; ++f) {
+        const W pat = lp.word(0, f, lo, k);
+        if (pat) lds_or<W>(&lds[lds_word<S_WORDS, sizeof(W) / 4>(lb, static_cast<uint32_t>(f))], pat);
+      }
     }
   }
 };
