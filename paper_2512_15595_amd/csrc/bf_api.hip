@@ -211,15 +211,16 @@ bf_status bfhip::alloc_filter_words(bf_filter* f) {
 
 // Strategy of one bulk add: partitioned when asked for, or (auto) when the
 // batch is dense enough for streaming the touched chunks to beat one
-// memory-side atomic group per key.  Measured crossover on MI355X: about
-// 2^21 keys for filters up to 64 MiB (few chunks: the apply is split over
-// many workgroups), about filter bytes / 48 keys beyond (each touched chunk
-// is read and written once).
+// memory-side atomic group per key.  Measured on MI355X (8 x 32-bit blocks,
+// 2^16..2^26 keys, 4 MiB..1 GiB): a partitioned add costs ~34 us + 0.45 ms
+// per GB of filter (each touched chunk read and written once) + 10 ms per
+// 10^9 keys, a direct add 40 (caches) to 51 (HBM) ms per 10^9 keys; the
+// crossover is about 1.5 M keys + filter bytes / 80.
 bool bfhip::use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
   if (m.strategy == BF_STRATEGY_DIRECT) return false;
   if (!partition_applicable(f, n)) return false;
   if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
-  return n >= (1ull << 22) && n >= f->nbytes / 48;
+  return n >= 3 * (1ull << 19) + f->nbytes / 80;
 }
 
 extern "C" {
