@@ -27,7 +27,8 @@ if ROOT not in sys.path:
 METRIC = "Gkeys/s add+contains, 1 GiB blocked BF, % random-gather bound; p99 served"
 PEAK_HBM_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
-KERNEL_SOURCES = ["bf_kernels.hpp", "bf_hash.hpp", "bf_tuned_defaults.inc"]  # the timed kernels and their mappings
+# the timed kernels (lookups; direct and partitioned adds) and their mappings
+KERNEL_SOURCES = ["bf_kernels.hpp", "bf_hash.hpp", "bf_tuned_defaults.inc", "bf_partition.hpp"]
 
 
 def log(msg: str) -> None:
@@ -875,7 +876,7 @@ def main() -> int:
     import torch
 
     from paper_2512_15595_amd import workloads
-    from paper_2512_15595_amd.bf import BF_OP_ADD, BF_OP_CONTAINS, BloomFilter
+    from paper_2512_15595_amd.bf import BF_OP_ADD, BF_OP_CONTAINS, BF_STRATEGY_PARTITIONED, BloomFilter
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
@@ -933,6 +934,7 @@ def main() -> int:
     info = f.info()
     mapping = {"add": info.mapping[BF_OP_ADD].as_dict(),
                "contains": info.mapping[BF_OP_CONTAINS].as_dict()}
+    add_partitioned = f.add_strategy(n) == BF_STRATEGY_PARTITIONED
 
     times = {"clear": [], "add": [], "contains": []}
 
@@ -996,6 +998,18 @@ def main() -> int:
                 "traffic": traffic, "algorithmic_bytes_per_key": per_key,
                 "avg_launch_ms": round(dom_ms, 4)}
 
+    # the add beside it: algorithmic bytes (a random read-modify-write of the
+    # block per key) against the HBM peak; `traffic` is the measured HBM bytes
+    # of the whole add (the three partitioned kernels, or the direct one)
+    add_per_key = 8 + 2 * block_bytes
+    add_achieved = add_per_key * n / (ms["add"] * 1e-3) / 1e9
+    roofline_add = {"bound": "hbm",
+                    "kernels": ("part_scatter1 + part_scatter2 + part_apply" if add_partitioned
+                                else "bf_add_kernel"),
+                    "achieved": round(add_achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": round(add_achieved / PEAK_HBM_GBS, 4), "traffic": committed_traffic("add", n),
+                    "algorithmic_bytes_per_key": add_per_key, "avg_launch_ms": round(ms["add"], 4)}
+
     result = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -1021,6 +1035,7 @@ def main() -> int:
         "false_positive_rate_0pct_hits": fp / n,
         "wall_s_timed": round(wall, 3),
         "roofline": roofline,
+        "roofline_add": roofline_add,
     }
     if copy_gbs is not None:
         result["copy_1GiB_gbs"] = round(copy_gbs, 1)

@@ -176,6 +176,16 @@ bf_status bf_set_mapping(bf_filter *f, int op, uint32_t lanes_per_key,
 /* Full form of bf_set_mapping (all fields of bf_mapping_t). */
 bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
 
+/* The construction strategy bf_add(f, keys, n, ...) takes with f's current
+ * add mapping: BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED, the automatic
+ * choice resolved by the measured crossover (partitioned from about 1.5 M
+ * keys + filter bytes / 80; for the classic layout n counts k records per
+ * key).  For callers that plan workspace memory (17-21 bytes per key for a
+ * partitioned add) or stream ordering (a partitioned add owns its filter
+ * while it runs).  Host only: enqueues nothing and touches no device.
+ * BF_EINVAL if f or out is NULL. */
+bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
+
 /* Static description of a status code. */
 const char *bf_strerror(bf_status s);
 

@@ -92,6 +92,8 @@ _lib.bf_clear.argtypes = [_vp, _vp]
 _lib.bf_clear.restype = _i32
 _lib.bf_info.argtypes = [_vp, ctypes.POINTER(bf_info_t)]
 _lib.bf_info.restype = _i32
+_lib.bf_add_strategy.argtypes = [_vp, _u64, ctypes.POINTER(_u32)]
+_lib.bf_add_strategy.restype = _i32
 _lib.bf_set_mapping.argtypes = [_vp, ctypes.c_int, _u32, _u32, _u32]
 _lib.bf_set_mapping.restype = _i32
 _lib.bf_set_mapping_ex.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(bf_mapping_t)]
@@ -264,6 +266,14 @@ def bf_info(f):
     return st, info
 
 
+def bf_add_strategy(f, n: int):
+    """Returns (status, BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED): the
+    construction an add of n keys takes with the filter's current mapping."""
+    out = _u32(0)
+    st = _lib.bf_add_strategy(f, n, ctypes.byref(out))
+    return st, out.value
+
+
 def bf_set_mapping(f, op: int, lanes_per_key: int, words_per_lane: int, keys_per_lane: int) -> int:
     return _lib.bf_set_mapping(f, op, lanes_per_key, words_per_lane, keys_per_lane)
 
@@ -388,6 +398,13 @@ class _Filter:
         st, info = bf_info(self._h)
         _check(st, "bf_info")
         return info
+
+    def add_strategy(self, n: int) -> int:
+        """BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED: how an add of n keys
+        is built with the current mapping."""
+        st, strategy = bf_add_strategy(self._h, n)
+        _check(st, "bf_add_strategy")
+        return strategy
 
     def set_mapping(self, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
                     keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0,

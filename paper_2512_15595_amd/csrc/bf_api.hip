@@ -129,7 +129,7 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
     return variant_launch(f, op, keys, n, out, static_cast<hipStream_t>(stream));
   ensure_registry();
   bf_mapping_t m = resolve_mapping(f, op);
-  if (op == BF_OP_ADD && use_partitioned(f, n, f->mapping[BF_OP_ADD]))
+  if (op == BF_OP_ADD && add_partitions(f, n))
     return partitioned_add(f, keys, n, static_cast<hipStream_t>(stream));
   // Keys per lane needs 8*KT-byte aligned keys (and KT-byte aligned results);
   // fall back to fewer keys per lane otherwise.
@@ -221,6 +221,11 @@ bool bfhip::use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& 
   if (!partition_applicable(f, n)) return false;
   if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
   return n >= 3 * (1ull << 19) + f->nbytes / 80;
+}
+
+bool bfhip::add_partitions(const bf_filter* f, uint64_t n) {
+  const uint64_t records = f->layout == BF_LAYOUT_CLASSIC ? n * f->k : n;
+  return use_partitioned(f, records, f->mapping[BF_OP_ADD]);
 }
 
 extern "C" {
@@ -342,6 +347,12 @@ bf_status bf_info(const bf_filter* f, bf_info_t* out) {
   i.groups = f->groups;
   i.num_bits = f->num_bits;
   *out = i;
+  return BF_OK;
+}
+
+bf_status bf_add_strategy(const bf_filter* f, uint64_t n, uint32_t* out) {
+  if (f == nullptr || out == nullptr) return BF_EINVAL;
+  *out = add_partitions(f, n) ? BF_STRATEGY_PARTITIONED : BF_STRATEGY_DIRECT;
   return BF_OK;
 }
 

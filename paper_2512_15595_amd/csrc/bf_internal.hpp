@@ -60,6 +60,9 @@ bf_status alloc_filter_words(bf_filter* f);
 
 // Whether a bulk add of n keys takes the partitioned strategy (bf_api.hip).
 bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m);
+// Whether bf_add of n keys on f takes the partitioned construction (the
+// classic layout counts k records per key).
+bool add_partitions(const bf_filter* f, uint64_t n);
 
 // The classic and cache-sectorized layouts (bf_variants.hip).
 bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op);

@@ -49,9 +49,9 @@ constexpr int kPartStep = 8192;                     // records per LDS-staged sc
 // Workgroup shapes of the scatter passes (threads; each thread holds
 // kPartStep / threads records of a step).  Measured on MI355X, one wide
 // workgroup per CU with a long step beats several narrow ones: both passes
-// run 16 waves of 8 records (a step's 64 KiB stage then fills most of the
-// CU's LDS); the classic first pass keeps 16 records per thread for up to
-// 16 positions per key.
+// run 16 waves of 8 records (a step's 64 KiB stage and the digit tables
+// take 88 of the CU's 160 KiB of LDS); the classic first pass keeps 16
+// records per thread for up to 16 positions per key.
 constexpr int kScatter1Threads = 1024;
 constexpr int kScatter2Threads = 1024;
 constexpr int kClassicThreads = 512;

@@ -66,7 +66,7 @@ struct StreamCtx {
 uint64_t payload_bytes(const bf_filter* f, const bf_request_t& r) {
   if (r.op == BF_OP_CONTAINS) return r.n * 9ull;
   uint64_t bytes = r.n * 8ull;
-  if (use_partitioned(f, r.n, f->mapping[BF_OP_ADD])) bytes += partition_workspace_bytes(f, r.n);
+  if (add_partitions(f, r.n)) bytes += partition_workspace_bytes(f, r.n);
   return bytes;
 }
 

@@ -200,11 +200,7 @@ bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_
 bf_status variant_launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                          hipStream_t stream) {
   ensure_variant_registry();
-  // a classic key is k records of the partitioned construction
-  const uint64_t records = f->layout == BF_LAYOUT_CLASSIC ? n * f->k : n;
-  if (op == BF_OP_ADD && f->layout != BF_LAYOUT_SECTORIZED_CHAINED &&
-      use_partitioned(f, records, f->mapping[BF_OP_ADD]))
-    return partitioned_add(f, keys, n, stream);
+  if (op == BF_OP_ADD && add_partitions(f, n)) return partitioned_add(f, keys, n, stream);
   const bf_mapping_t m = variant_resolve_mapping(f, op);
   uint32_t kt = m.keys_per_lane;
   while (kt > 1 && ((reinterpret_cast<uintptr_t>(keys) % (8u * kt)) != 0 ||

@@ -35,7 +35,7 @@ def test_headers_declare_the_boundary():
     for required in ("bf_create", "bf_create_in", "bf_create_classic", "bf_create_csbf",
                      "bf_create_chained",
                      "bf_destroy", "bf_add",
-                     "bf_contains", "bf_clear", "bf_info",
+                     "bf_contains", "bf_clear", "bf_info", "bf_add_strategy",
                      "bf_set_mapping", "bf_strerror", "bfb_random_read", "bfb_random_atomic_or",
                      "bfb_gups", "bfb_copy"):
         assert required in names
@@ -73,6 +73,8 @@ def test_binding_loads_and_validates_without_gpu():
     assert bf.bf_set_mapping(None, 0, 1, 1, 1) == bf.BF_EINVAL
     assert bf.bf_destroy(None) == bf.BF_OK
     st, _ = bf.bf_info(None)
+    assert st == bf.BF_EINVAL
+    st, _ = bf.bf_add_strategy(None, 1 << 20)
     assert st == bf.BF_EINVAL
     assert bf.bf_strerror(bf.BF_EINVAL) == "invalid argument"
     assert bf.bf_strerror(12345) == "unknown status"

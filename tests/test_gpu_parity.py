@@ -244,6 +244,36 @@ def test_auto_strategy_matches_direct():
     assert np.array_equal(rows, want)
 
 
+def test_add_strategy_reports_the_construction():
+    """bf_add_strategy resolves the automatic choice as bf_add does: direct
+    below about 1.5 M keys + filter bytes / 80, partitioned above; a forced
+    strategy wins; the classic layout counts k records per key; the chained
+    layout is never partitioned."""
+    bf = _bf()
+    f = bf.BloomFilter(1 << 20, 8, 32, 8, 3)                 # 32 MiB
+    try:
+        assert f.add_strategy(0) == bf.BF_STRATEGY_DIRECT
+        assert f.add_strategy(1 << 20) == bf.BF_STRATEGY_DIRECT
+        assert f.add_strategy(1 << 22) == bf.BF_STRATEGY_PARTITIONED
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_DIRECT)
+        assert f.add_strategy(1 << 22) == bf.BF_STRATEGY_DIRECT
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        assert f.add_strategy(10) == bf.BF_STRATEGY_PARTITIONED
+    finally:
+        f.close()
+    c = bf.ClassicFilter(1 << 28, 8, 1)                      # 32 MiB, 8 records per key
+    try:
+        assert c.add_strategy(1 << 17) == bf.BF_STRATEGY_DIRECT
+        assert c.add_strategy(1 << 18) == bf.BF_STRATEGY_PARTITIONED
+    finally:
+        c.close()
+    h = bf.ChainedHashFilter(1 << 20, 8, 32, 8, 3)
+    try:
+        assert h.add_strategy(1 << 24) == bf.BF_STRATEGY_DIRECT
+    finally:
+        h.close()
+
+
 def test_partitioned_overflow_with_repeated_keys():
     """Repeated keys pile into one chunk beyond its bucket capacity; the
     overflowing records take the direct-atomic fallback and the words still
