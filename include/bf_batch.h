@@ -12,14 +12,17 @@
  * keys per lane) by the filter's size class from the autotuned table, and
  * records one persistent kernel launch in a HIP graph.
  *
- * An add plan whose keys are dense enough over its filters (the rule of
- * BF_STRATEGY_AUTO in bf.h, applied to all filters together) is instead
- * planned as one partitioned construction over every filter: the filters'
- * blocks are laid end to end in one block space, one radix partition
- * groups all keys by 64 KiB chunk, and each chunk is updated in LDS (four
- * kernels in the graph).  Filter 0's add strategy (bf_set_mapping_ex) can
- * force BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED.  The partitioned
- * plan owns its filters while it runs, like a partitioned bf_add.
+ * An add plan with enough keys on filters that are dense (at least their
+ * bytes / 80 keys each: the per-filter form of the BF_STRATEGY_AUTO rule in
+ * bf.h) and at least 512 chunks among them is instead planned as one
+ * partitioned construction over the dense filters: the filters' blocks are
+ * laid end to end in one block space, one radix partition groups their keys
+ * by 64 KiB chunk, and each chunk is updated in LDS (four kernels in the
+ * graph); the keys of the sparse filters go to the tiled launch, recorded
+ * after them, so no sparse filter's words are streamed.  Filter 0's add
+ * strategy (bf_set_mapping_ex) can force BF_STRATEGY_DIRECT (tiles only) or
+ * BF_STRATEGY_PARTITIONED (every filter partitioned).  The partitioned plan
+ * owns its filters while it runs, like a partitioned bf_add.
  *
  * All filters of a plan must share words_per_block, word_bits and k.  Keys
  * of filter i are d_keys[h_offsets[i] .. h_offsets[i+1]) (device memory,
@@ -47,8 +50,10 @@ typedef struct {
   uint32_t op;             /* BF_OP_ADD or BF_OP_CONTAINS */
   uint32_t nfilters;
   uint64_t nkeys;          /* h_offsets[nfilters] - h_offsets[0] */
-  uint64_t ntiles;         /* tile slots in the launch (including padding) */
-  uint32_t grid;           /* workgroups of the persistent launch (first pass if partitioned) */
+  uint64_t ntiles;         /* tile slots in the launch (including padding); of a
+                              partitioned plan: those of its sparse filters */
+  uint32_t grid;           /* workgroups of the persistent launch (first pass if
+                              partitioned with no tiles) */
   uint32_t tiles_per_class[3]; /* L2 / Infinity-Cache / HBM sized filters */
   bf_mapping_t mapping[3]; /* mapping compiled in per size class */
   uint32_t strategy;       /* BF_STRATEGY_DIRECT (tiles) or BF_STRATEGY_PARTITIONED */

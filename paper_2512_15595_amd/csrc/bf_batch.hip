@@ -42,8 +42,10 @@ struct bf_batch {
   BatchArgs args;
   hipGraph_t graph;
   hipGraphExec_t exec;
-  // partitioned construction over all filters of the plan (add only)
+  // partitioned construction over the dense filters of the plan (add only);
+  // part_direct[i] marks the filters left to the tiled direct launch
   bool partitioned;
+  std::vector<uint8_t> part_direct;
   PartArgs part;
   PartLayout part_layout;
   PartKernels part_k;
@@ -66,19 +68,25 @@ void free_plan(bf_batch* b) {
   delete b;
 }
 
-// Partitioned construction for a whole add plan: the filters' blocks are
-// laid end to end in one global block space (each filter starting on a
-// chunk boundary), so one radix partition groups every key of every filter
-// by global chunk.  Returns BF_OK and sets b->partitioned when taken.
+// Partitioned construction for an add plan: the filters' blocks are laid
+// end to end in one global block space (each filter starting on a chunk
+// boundary), so one radix partition groups every key of every filter by
+// global chunk.  With the automatic strategy a filter with fewer keys than
+// its bytes / 80 is left to the direct launch (b->part_direct): streaming
+// its chunks would cost more than its keys' atomics (the single-filter
+// crossover of the same construction), and its chunks then get neither
+// records nor traffic.  Returns BF_OK and sets b->partitioned when taken.
 bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfilters,
                            const uint64_t* d_keys, const uint64_t* h_offsets) {
   const bf_filter* f0 = filters[0];
   const uint32_t strategy = f0->mapping[BF_OP_ADD].strategy;
   if (strategy == BF_STRATEGY_DIRECT) return BF_OK;
+  const bool forced = strategy == BF_STRATEGY_PARTITIONED;
+  uint64_t n_dense = 0, dense_chunks = 0;
   const uint32_t shift = part_chunk_shift(f0->s, f0->word_bits);
   const uint64_t bpc = 1ull << shift;
   std::vector<PartFilter> pf(nfilters);
-  uint64_t chunks = 0, total_bytes = 0;
+  uint64_t chunks = 0;
   for (uint32_t i = 0; i < nfilters; ++i) {
     const bf_filter* f = filters[i];
     pf[i].words = f->d_words;
@@ -90,14 +98,18 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
     pf[i].block_base = chunks * bpc;
     pf[i].key_begin = h_offsets[i] - h_offsets[0];
     pf[i].key_end = h_offsets[i + 1] - h_offsets[0];
-    chunks += (f->num_blocks + bpc - 1) / bpc;
-    total_bytes += f->nbytes;
+    const uint64_t ni = pf[i].key_end - pf[i].key_begin;
+    const uint64_t nc = (f->num_blocks + bpc - 1) / bpc;
+    pf[i].direct = !forced && ni * 80 < f->nbytes ? 1u : 0u;
+    if (!pf[i].direct) {
+      n_dense += ni;
+      dense_chunks += nc;
+    }
+    chunks += nc;
   }
   const uint64_t n = h_offsets[nfilters] - h_offsets[0];
   if (n == 0 || chunks * bpc > (1ull << 32)) return BF_OK;  // global blocks must fit 32 bits
-  if (strategy == BF_STRATEGY_AUTO &&
-      !(chunks >= 512 && n >= (1ull << 21) && n >= total_bytes / 48))
-    return BF_OK;
+  if (strategy == BF_STRATEGY_AUTO && !(dense_chunks >= 512 && n_dense >= (1ull << 21))) return BF_OK;
   PartArgs a{};
   PartLayout L{};
   if (!part_geometry(chunks, shift, n, a, L)) return BF_OK;
@@ -109,7 +121,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   std::vector<double> load(chunks, 0.0);
   for (uint32_t i = 0; i < nfilters; ++i) {
     const double ni = static_cast<double>(pf[i].key_end - pf[i].key_begin);
-    if (ni == 0) continue;
+    if (ni == 0 || pf[i].direct) continue;
     const uint64_t nc = (pf[i].num_blocks + bpc - 1) / bpc;
     for (uint64_t c = 0; c < nc; ++c) {
       const uint64_t blocks = std::min<uint64_t>(bpc, pf[i].num_blocks - c * bpc);
@@ -165,6 +177,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
       work2.push_back(PartWork{d, static_cast<uint16_t>(i), static_cast<uint16_t>(ns)});
   }
   for (uint64_t c = 0; c < chunks; ++c) {
+    if (load[c] <= 0.0) continue;  // no records can land here: nothing to apply
     const uint64_t ns = std::clamp<uint64_t>(static_cast<uint64_t>(load[c] / 131072.0) + 1, 1, 65535);
     for (uint64_t i = 0; i < ns; ++i)
       work3.push_back(PartWork{static_cast<uint32_t>(c), static_cast<uint16_t>(i), static_cast<uint16_t>(ns)});
@@ -216,105 +229,57 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   b->part_layout = L;
   b->part_k = k;
   b->partitioned = true;
+  b->part_direct.resize(nfilters);
+  for (uint32_t i = 0; i < nfilters; ++i) b->part_direct[i] = static_cast<uint8_t>(pf[i].direct);
   return BF_OK;
 }
 
-bf_status build_partitioned_graph(bf_batch* b) {
+// The plan's graph: the partitioned construction's four kernels (when
+// taken), then the persistent tiled launch (when it has tiles, or when the
+// plan is not partitioned).
+bf_status build_graph(bf_batch* b) {
   hipGraphNode_t prev = nullptr, node = nullptr;
-  unsigned long long* fills = b->part.fill1;
-  uint64_t nfill = b->part_layout.nfill;
-  void* zargs[] = {&fills, &nfill};
-  void* pargs[] = {&b->part};
-  struct Step {
-    const void* fn;
-    dim3 grid, block;
-    void** args;
-  } steps[] = {
-      {reinterpret_cast<const void*>(&part_zero_kernel),
-       dim3(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>((nfill + 255) / 256, 4096)))),
-       dim3(kZeroThreads), zargs},
-      {b->part_k.scatter1, part_grid1(b->part), dim3(b->part_k.threads1), pargs},
-      {b->part_k.scatter2, part_grid2(b->part), dim3(kScatter2Threads), pargs},
-      {b->part_k.apply, part_grid3(b->part), dim3(kApplyThreads), pargs},
-  };
   if (hipGraphCreate(&b->graph, 0) != hipSuccess) return BF_EDEVICE;
-  for (const Step& st : steps) {
+  auto add_node = [&](const void* fn, dim3 grid, dim3 block, void** args) {
     hipKernelNodeParams p{};
-    p.func = const_cast<void*>(st.fn);
-    p.gridDim = st.grid;
-    p.blockDim = st.block;
+    p.func = const_cast<void*>(fn);
+    p.gridDim = grid;
+    p.blockDim = block;
     p.sharedMemBytes = 0;
-    p.kernelParams = st.args;
+    p.kernelParams = args;
     p.extra = nullptr;
-    if (hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) !=
-        hipSuccess)
-      return BF_EDEVICE;
+    if (hipGraphAddKernelNode(&node, b->graph, prev ? &prev : nullptr, prev ? 1 : 0, &p) != hipSuccess)
+      return false;
     prev = node;
+    return true;
+  };
+  if (b->partitioned) {
+    unsigned long long* fills = b->part.fill1;
+    uint64_t nfill = b->part_layout.nfill;
+    void* zargs[] = {&fills, &nfill};
+    void* pargs[] = {&b->part};
+    const dim3 zgrid(static_cast<uint32_t>(std::max<uint64_t>(1, std::min<uint64_t>((nfill + 255) / 256, 4096))));
+    if (!add_node(reinterpret_cast<const void*>(&part_zero_kernel), zgrid, dim3(kZeroThreads), zargs) ||
+        !add_node(b->part_k.scatter1, part_grid1(b->part), dim3(b->part_k.threads1), pargs) ||
+        !add_node(b->part_k.scatter2, part_grid2(b->part), dim3(kScatter2Threads), pargs) ||
+        !add_node(b->part_k.apply, part_grid3(b->part), dim3(kApplyThreads), pargs))
+      return BF_EDEVICE;
+  }
+  if (!b->partitioned || b->ntiles > 0) {
+    void* kargs[] = {&b->args};
+    if (!add_node(b->fn, dim3(b->grid), dim3(kBlockThreads), kargs)) return BF_EDEVICE;
   }
   return hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) == hipSuccess ? BF_OK
                                                                                      : BF_EDEVICE;
 }
 
-}  // namespace
-
-extern "C" {
-
-bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
-                        const uint64_t* d_keys, const uint64_t* h_offsets, uint8_t* d_out,
-                        bf_batch** out) {
-  if (out == nullptr || filters == nullptr || h_offsets == nullptr || nfilters == 0)
-    return BF_EINVAL;
-  if (op != BF_OP_ADD && op != BF_OP_CONTAINS) return BF_EINVAL;
+// The tiled direct plan: every key of the selected filters (all when
+// `only` is null) in tiles of one persistent launch.  Filters go to the 8
+// XCD queues by longest-processing-time on their key counts.
+bf_status build_tiles(bf_batch* b, bf_filter* const* filters, uint32_t nfilters, const uint64_t* d_keys,
+                      const uint64_t* h_offsets, uint8_t* d_out, const std::vector<uint8_t>* only) {
+  const int op = b->op;
   const bf_filter* f0 = filters[0];
-  if (f0 == nullptr) return BF_EINVAL;
-  for (uint32_t i = 0; i < nfilters; ++i) {
-    const bf_filter* f = filters[i];
-    if (f != nullptr && f->layout != BF_LAYOUT_SECTORIZED) return BF_EUNSUPPORTED;
-    if (f == nullptr || f->s != f0->s || f->word_bits != f0->word_bits || f->k != f0->k ||
-        f->device != f0->device)
-      return BF_EINVAL;
-    if (h_offsets[i + 1] < h_offsets[i]) return BF_EINVAL;
-  }
-  const uint64_t nkeys = h_offsets[nfilters] - h_offsets[0];
-  if (nkeys > 0 && (d_keys == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0))
-    return BF_EINVAL;
-  if (op == BF_OP_CONTAINS && nkeys > 0 && d_out == nullptr) return BF_EINVAL;
-
-  ensure_registry();
-  const void* fn = registry().batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
-                                                   static_cast<int>(f0->s), k_index(f0->k))];
-  if (fn == nullptr) return BF_EUNSUPPORTED;
-
-  bf_batch* b = new (std::nothrow) bf_batch{};
-  if (b == nullptr) return BF_ENOMEM;
-  b->op = op;
-  b->nfilters = nfilters;
-  b->nkeys = nkeys;
-  b->filters.assign(filters, filters + nfilters);
-  b->offsets.assign(h_offsets, h_offsets + nfilters + 1);
-  b->d_keys = d_keys;
-  b->d_out = d_out;
-  b->fn = fn;
-
-  if (op == BF_OP_ADD) {
-    bf_status pst = plan_partitioned(b, filters, nfilters, d_keys, h_offsets);
-    if (pst != BF_OK) {
-      free_plan(b);
-      return pst;
-    }
-    if (b->partitioned) {
-      b->ntiles = 0;
-      b->grid = part_grid1(b->part).x;
-      if (build_partitioned_graph(b) != BF_OK) {
-        (void)hipGetLastError();
-        free_plan(b);
-        return BF_EDEVICE;
-      }
-      *out = b;
-      return BF_OK;
-    }
-  }
-
   // Mapping per size class (identical for all filters of a class).
   for (int c = 0; c < kNumSizeClasses; ++c) {
     const MapSpec m = class_map(op, f0, c);
@@ -326,7 +291,6 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
     b->mapping[c] = bm;
   }
 
-  // Filters go to XCD queues by longest-processing-time on their key counts.
   std::vector<uint32_t> order(nfilters);
   std::iota(order.begin(), order.end(), 0u);
   std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
@@ -336,7 +300,7 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   std::vector<uint64_t> load(kXcds, 0);
   for (uint32_t i : order) {
     const uint64_t n = h_offsets[i + 1] - h_offsets[i];
-    if (n == 0) continue;
+    if (n == 0 || (only != nullptr && !(*only)[i])) continue;
     const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
     load[x] += n;
     const bf_filter* f = filters[i];
@@ -389,14 +353,12 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   if (hipMalloc(&b->d_filters, descs.size() * sizeof(BatchFilter)) != hipSuccess ||
       hipMalloc(&b->d_tiles, tiles_bytes) != hipSuccess) {
     (void)hipGetLastError();
-    free_plan(b);
     return BF_ENOMEM;
   }
   if (hipMemcpy(b->d_filters, descs.data(), descs.size() * sizeof(BatchFilter),
                 hipMemcpyHostToDevice) != hipSuccess ||
       (!tiles.empty() && hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
                                    hipMemcpyHostToDevice) != hipSuccess)) {
-    free_plan(b);
     return BF_EDEVICE;
   }
 
@@ -405,19 +367,76 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   b->args.ntiles = b->ntiles;
   b->args.k = f0->k;
 
-  // The graph: one kernel node, the persistent launch.
-  hipKernelNodeParams p{};
-  void* kargs[] = {&b->args};
-  p.func = const_cast<void*>(fn);
-  p.gridDim = dim3(b->grid);
-  p.blockDim = dim3(kBlockThreads);
-  p.sharedMemBytes = 0;
-  p.kernelParams = kargs;
-  p.extra = nullptr;
-  hipGraphNode_t node;
-  if (hipGraphCreate(&b->graph, 0) != hipSuccess ||
-      hipGraphAddKernelNode(&node, b->graph, nullptr, 0, &p) != hipSuccess ||
-      hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess) {
+  return BF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
+                        const uint64_t* d_keys, const uint64_t* h_offsets, uint8_t* d_out,
+                        bf_batch** out) {
+  if (out == nullptr || filters == nullptr || h_offsets == nullptr || nfilters == 0)
+    return BF_EINVAL;
+  if (op != BF_OP_ADD && op != BF_OP_CONTAINS) return BF_EINVAL;
+  const bf_filter* f0 = filters[0];
+  if (f0 == nullptr) return BF_EINVAL;
+  for (uint32_t i = 0; i < nfilters; ++i) {
+    const bf_filter* f = filters[i];
+    if (f != nullptr && f->layout != BF_LAYOUT_SECTORIZED) return BF_EUNSUPPORTED;
+    if (f == nullptr || f->s != f0->s || f->word_bits != f0->word_bits || f->k != f0->k ||
+        f->device != f0->device)
+      return BF_EINVAL;
+    if (h_offsets[i + 1] < h_offsets[i]) return BF_EINVAL;
+  }
+  const uint64_t nkeys = h_offsets[nfilters] - h_offsets[0];
+  if (nkeys > 0 && (d_keys == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0))
+    return BF_EINVAL;
+  if (op == BF_OP_CONTAINS && nkeys > 0 && d_out == nullptr) return BF_EINVAL;
+
+  ensure_registry();
+  const void* fn = registry().batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
+                                                   static_cast<int>(f0->s), k_index(f0->k))];
+  if (fn == nullptr) return BF_EUNSUPPORTED;
+
+  bf_batch* b = new (std::nothrow) bf_batch{};
+  if (b == nullptr) return BF_ENOMEM;
+  b->op = op;
+  b->nfilters = nfilters;
+  b->nkeys = nkeys;
+  b->filters.assign(filters, filters + nfilters);
+  b->offsets.assign(h_offsets, h_offsets + nfilters + 1);
+  b->d_keys = d_keys;
+  b->d_out = d_out;
+  b->fn = fn;
+
+  if (op == BF_OP_ADD) {
+    bf_status pst = plan_partitioned(b, filters, nfilters, d_keys, h_offsets);
+    if (pst != BF_OK) {
+      free_plan(b);
+      return pst;
+    }
+  }
+  // The tiled direct launch: every filter, or (partitioned plan) the filters
+  // left to it that have keys.
+  bool tiled = !b->partitioned;
+  if (b->partitioned)
+    for (uint32_t i = 0; i < nfilters; ++i)
+      tiled = tiled || (b->part_direct[i] && h_offsets[i + 1] > h_offsets[i]);
+  if (tiled) {
+    const bf_status st =
+        build_tiles(b, filters, nfilters, d_keys, h_offsets, d_out, b->partitioned ? &b->part_direct : nullptr);
+    if (st != BF_OK) {
+      (void)hipGetLastError();
+      free_plan(b);
+      return st;
+    }
+  } else {
+    b->ntiles = 0;
+    b->grid = part_grid1(b->part).x;
+  }
+  if (build_graph(b) != BF_OK) {
     (void)hipGetLastError();
     free_plan(b);
     return BF_EDEVICE;
@@ -435,8 +454,10 @@ bf_status bf_batch_launch(bf_batch* b, void* stream) {
 
 bf_status bf_batch_launch_direct(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
-  if (b->partitioned)
-    return part_launch(b->part, b->part_layout, b->part_k, static_cast<hipStream_t>(stream));
+  if (b->partitioned) {
+    const bf_status st = part_launch(b->part, b->part_layout, b->part_k, static_cast<hipStream_t>(stream));
+    if (st != BF_OK) return st;
+  }
   if (b->ntiles == 0) return BF_OK;
   void* kargs[] = {&b->args};
   return hipLaunchKernel(b->fn, dim3(b->grid), dim3(kBlockThreads), kargs, 0,

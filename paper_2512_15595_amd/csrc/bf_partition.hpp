@@ -67,7 +67,9 @@ static_assert(kVecPerThread * 16 * kApplyThreads == kChunkBytes, "apply covers a
 // One filter of a multi-filter partitioned add.  Its blocks occupy global
 // blocks [block_base, block_base + num_blocks) and its chunks global chunks
 // from chunk_base (block_base is a multiple of the blocks per chunk); its
-// keys are keys[key_begin, key_end).
+// keys are keys[key_begin, key_end).  A `direct` filter (few keys for its
+// size) takes no part: its keys are left to a direct launch, so none of its
+// chunks is read or written here.
 struct PartFilter {
   void* words;
   uint64_t hash_init;
@@ -78,6 +80,8 @@ struct PartFilter {
   uint64_t chunk_base;
   uint64_t key_begin;
   uint64_t key_end;
+  uint32_t direct;
+  uint32_t reserved;
 };
 
 struct PartArgs {
@@ -328,8 +332,9 @@ __device__ __forceinline__ void slice_walk(const uint32_t* pre, uint32_t& i0, ui
 }
 
 // One LDS-staged scatter step.  The records r[] of this thread that take
-// part (valid_of(j), `total` of them over the workgroup; record j sits at
-// position tid + j * THREADS) with digits dg[] are grouped by digit.
+// part (valid_of(j); record j sits at position tid + j * THREADS) with
+// digits dg[] are grouped by digit; *ntotal (LDS) receives their number
+// over the workgroup.
 // For every digit d with records, claim(d, cnt, gbase[d], room[d]) reserves
 // a run of cnt records in digit d's destination: the run starts at record
 // gbase[d] of buf and its first room[d] <= cnt records fit; the others go
@@ -340,8 +345,8 @@ __device__ __forceinline__ void slice_walk(const uint32_t* pre, uint32_t& i0, ui
 template <int THREADS, typename ValidOf, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step_masked(
     const uint64_t (&r)[kPartStep / THREADS], const uint32_t (&dg)[kPartStep / THREADS], ValidOf valid_of,
-    uint32_t total, uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start, uint64_t* gbase,
-    uint32_t* room, uint64_t* buf, DigitOf digit_of, Claim claim, Overflow overflow) {
+    uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start, uint64_t* gbase, uint32_t* room,
+    uint32_t* ntotal, uint64_t* buf, DigitOf digit_of, Claim claim, Overflow overflow) {
   constexpr int PER = kPartStep / THREADS;
   uint32_t rank[PER];
 #pragma unroll
@@ -369,8 +374,10 @@ __device__ __forceinline__ void scatter_step_masked(
       start[d] = run;
       run += cnt[d];
     }
+    if (threadIdx.x == 63) *ntotal = incl;
   }
   __syncthreads();
+  const uint32_t total = *ntotal;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
     if (valid_of(j)) stage[start[dg[j]] + rank[j]] = r[j];
@@ -407,11 +414,11 @@ template <int THREADS, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartStep / THREADS],
                                              const uint32_t (&dg)[kPartStep / THREADS], uint32_t valid,
                                              uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start,
-                                             uint64_t* gbase, uint32_t* room, uint64_t* buf, DigitOf digit_of,
-                                             Claim claim, Overflow overflow) {
+                                             uint64_t* gbase, uint32_t* room, uint32_t* ntotal, uint64_t* buf,
+                                             DigitOf digit_of, Claim claim, Overflow overflow) {
   scatter_step_masked<THREADS>(
-      r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, valid, ndigits, stage, cnt, start,
-      gbase, room, buf, digit_of, claim, overflow);
+      r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, ndigits, stage, cnt, start, gbase,
+      room, ntotal, buf, digit_of, claim, overflow);
 }
 
 // A run of c records at offset b of a destination of cap records: how many fit.
@@ -428,6 +435,7 @@ struct ScatterLds {
   uint32_t start[D];
   uint32_t room[D];
   uint32_t fill[D];  // sliced mode: records written to this workgroup's slice
+  uint32_t total;    // records of the current step
 };
 
 // Destination of the first pass's digit d: slice (d, this workgroup) in
@@ -473,6 +481,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
   uint32_t cur = 0;
   uint64_t cur_end = ~0ull, cur_hinit = a.hash_init, cur_base = 0;
   uint32_t cur_lo = a.nb_lo, cur_hi = a.nb_hi_mask;
+  bool cur_direct = false;
   if constexpr (MULTI) {
     cur = a.wg_first[blockIdx.x];
     const PartFilter& f = a.filters[cur];
@@ -481,6 +490,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     cur_lo = f.nb_lo;
     cur_hi = f.nb_hi_mask;
     cur_base = f.block_base;
+    cur_direct = f.direct != 0;
   }
   // The keys of the next step are loaded while this step hashes and sorts
   // (workgroup barriers do not wait for global loads), so their latency is
@@ -503,6 +513,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     if (s + kPartStep < end) load_keys(s + kPartStep);
     uint64_t r[kPer1];
     uint32_t dg[kPer1];
+    bool take[kPer1];
 #pragma unroll
     for (int j = 0; j < kPer1; ++j) {
       if constexpr (MULTI) {
@@ -515,15 +526,18 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
           cur_lo = f.nb_lo;
           cur_hi = f.nb_hi_mask;
           cur_base = f.block_base;
+          cur_direct = f.direct != 0;
         }
       }
       const uint64_t h = xxh64_u64(key[j], cur_hinit);
       const uint32_t blk = static_cast<uint32_t>(cur_base + block_of(h, cur_lo, cur_hi));
       r[j] = (static_cast<uint64_t>(blk) << 32) | static_cast<uint32_t>(h);
       dg[j] = blk >> shift;
+      take[j] = threadIdx.x + j * kScatter1Threads < valid && !cur_direct;
     }
-    scatter_step<kScatter1Threads>(
-        r, dg, valid, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, a.buf1,
+    scatter_step_masked<kScatter1Threads>(
+        r, dg, [&take](int j) { return take[j]; }, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
+        a.buf1,
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
         [&](uint64_t v) {
@@ -595,8 +609,8 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
       dg[j] = 0;
     }
     scatter_step_masked<kClassicThreads>(
-        r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, vkeys * K, a.f1, l.stage, l.cnt, l.start,
-        l.gbase, l.room, a.buf1, [shift](uint64_t v) { return rec_block(v) >> shift; },
+        r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room,
+        &l.total, a.buf1, [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
         [&](uint64_t v) {
           rule.add_global(static_cast<uint32_t*>(a.words), rec_block(v), rec_lo(v), 0);
@@ -669,7 +683,7 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
       dg[j] = (rec_block(r[j]) >> cshift) & mask;
     }
     scatter_step<kScatter2Threads>(
-        r, dg, valid, f2, l.stage, l.cnt, l.start, l.gbase, l.room, a.buf2,
+        r, dg, valid, f2, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total, a.buf2,
         [cshift, mask](uint64_t v) { return (rec_block(v) >> cshift) & mask; },
         [&](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) {
           const uint64_t b = atomicAdd(&a.fill2[cbase + d], static_cast<unsigned long long>(c));

@@ -164,3 +164,41 @@ def test_batch_partitioned_add(mode):
     for j in range(len(params)):
         assert np.array_equal(words[j], want_words[j]), f"filter {j}"
     assert np.array_equal(out, want_out)
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct"])
+def test_batch_auto_add_splits_dense_and_sparse_filters(mode):
+    """The automatic add plan partitions the dense filters (at least bytes /
+    80 keys) and leaves the sparse ones, and the empty ones, to the tiled
+    launch recorded after it; every filter's words equal the oracle's."""
+    bf = _bf()
+    block = 32
+    g = workloads.rng(77)
+    dense = [(8 << 20, 300_000 + int(g.integers(0, 1000))) for _ in range(8)]  # 1024 chunks, 2.4 M keys
+    sparse = [(64 << 20, 5_000 + int(g.integers(0, 5000))) for _ in range(4)]
+    empty = [(1 << 20, 0), (64 << 20, 0)]
+    spec = dense[:4] + sparse[:2] + [empty[0]] + dense[4:] + sparse[2:] + [empty[1]]
+    counts = np.array([c for _, c in spec], dtype=np.int64)
+    offsets = np.zeros(len(spec) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    keys = workloads.uniform_keys(int(offsets[-1]), 78)
+    params = [dict(num_blocks=sz // block, words_per_block=8, word_bits=32, k=8, seed=500 + i)
+              for i, (sz, _) in enumerate(spec)]
+    log(f"batch auto split mode={mode}: {len(spec)} filters, {keys.size} keys")
+    want_words, _ = _oracle(params, offsets, keys, np.zeros(0, dtype=np.uint64))
+    filters = [bf.BloomFilter(**p) for p in params]
+    d_keys = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    add = bf.BatchPlan(bf.BF_OP_ADD, filters, d_keys, offsets)
+    try:
+        info = add.info()
+        assert info.strategy == bf.BF_STRATEGY_PARTITIONED
+        assert info.ntiles > 0                           # the sparse filters' tiles
+        (add.launch if mode == "graph" else add.launch_direct)()
+        words = [f.words().cpu().numpy() for f in filters]
+        torch.cuda.synchronize()
+    finally:
+        add.close()
+        for f in filters:
+            f.close()
+    for j in range(len(spec)):
+        assert np.array_equal(words[j], want_words[j]), f"filter {j}"
