@@ -84,6 +84,7 @@ def measure_bounds(torch, nbytes: int, seg: int, n_access: int, reps: int = 3) -
     lib.bfb_gups.argtypes = [vp, u64, u64, u32, vp]
     lib.bfb_fill_random_index.argtypes = [vp, u64, u64, u32, vp]
     lib.bfb_random_read_indexed.argtypes = [vp, u64, u32, vp, u64, vp, vp]
+    lib.bfb_random_read_policy.argtypes = [vp, u64, u32, u32, u64, u32, vp, vp]
 
     stream = torch.cuda.current_stream().cuda_stream
     buf = torch.zeros(nbytes, dtype=torch.uint8, device="cuda")
@@ -108,6 +109,13 @@ def measure_bounds(torch, nbytes: int, seg: int, n_access: int, reps: int = 3) -
         res[f"read_{s_bytes}B_x{lanes}"] = best(
             lambda r, s_bytes=s_bytes, lanes=lanes: lib.bfb_random_read(
                 buf.data_ptr(), nbytes, s_bytes, lanes, n_access, 1000 + r, sink.data_ptr(), stream))
+    # the same reads issued with explicit cache policies, eight loads in
+    # flight per thread (segments of 32 or 128 bytes only)
+    if seg in (32, 128):
+        for pol, name in ((1, "nt"), (2, "sc1"), (3, "sc0sc1"), (4, "ntsc1")):
+            res[f"read_{seg}B_{name}"] = best(
+                lambda r, pol=pol: lib.bfb_random_read_policy(
+                    buf.data_ptr(), nbytes, seg, pol, n_access, 1500 + r, sink.data_ptr(), stream))
     res[f"read_{seg}B_indexed"] = best(
         lambda r: lib.bfb_random_read_indexed(buf.data_ptr(), nbytes, seg, idx.data_ptr(), n_access,
                                               out.data_ptr(), stream))

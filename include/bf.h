@@ -31,11 +31,22 @@
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is enqueued and the status says why.  Launch failures are BF_EDEVICE.
  *     Faults inside a kernel surface at the caller's next synchronization.
- *   - Concurrency: direct-strategy bf_add calls on one filter from several
- *     streams commute; a partitioned-strategy add must be ordered against
- *     other writers of the filter.  A bf_contains that is not ordered after
- *     a bf_add (by stream order or events) may see any state between
- *     "before" and "after" that add.
+ *   - Concurrency: bf_add calls on one filter from any streams commute, as
+ *     OR does (Sec. II-A-1), under every construction strategy, with no
+ *     events of the caller's: the library records each call's last use of
+ *     the filter on its stream, makes a partitioned add (which loads whole
+ *     64 KiB chunks of words and stores them back) wait for every earlier
+ *     call on the filter, and makes a direct add wait for the last
+ *     partitioned add.  The calls of one filter are enqueued under that
+ *     filter's lock, so several host threads may call them at once.
+ *     bf_contains, bf_clear, bf_export_words and bf_import_words are ordered
+ *     by the caller against adds on other streams (stream order or events);
+ *     a bf_contains not ordered after a bf_add may see any state between
+ *     "before" and "after" that add.  Work enqueued while the stream is
+ *     being captured into a HIP graph is ordered by the capturing caller
+ *     (events recorded outside a capture cannot be waited on inside it).
+ *     Batched plans (bf_batch.h) and servers (bf_serve.h) order their own
+ *     launches; the caller orders them against bf.h calls on their filters.
  */
 #ifndef BF_H
 #define BF_H
@@ -82,10 +93,10 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *                   from a per-device stream-ordered memory pool and returns
  *                   it at its end on the same stream (no device
  *                   synchronization; the pool keeps its peak size reserved
- *                   for later adds), and while it runs it owns the filter:
- *                   another add on a different stream must be ordered
- *                   against it (events).  Mapping fields other than strategy
- *                   do not apply to it.  Results are identical. */
+ *                   for later adds); the library orders it against the
+ *                   filter's other adds on any stream (see Concurrency).
+ *                   Mapping fields other than strategy do not apply to it.
+ *                   Results are identical. */
 typedef struct {
   uint32_t lanes_per_key;
   uint32_t words_per_lane;
@@ -137,9 +148,11 @@ bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t w
                        uint32_t k, uint64_t seed, void *d_words, uint64_t nbytes,
                        bf_filter **out);
 
-/* Frees the words (after a device synchronization; not for bf_create_in
- * filters, whose words stay the caller's) and the handle.
- * NULL is accepted and ignored. */
+/* Waits until every bf.h call enqueued on this filter (on any stream) has
+ * finished -- other filters' work and other streams are not waited for --
+ * then frees the words (not for bf_create_in filters, whose words stay the
+ * caller's) and the handle.  The caller must not destroy a filter that a
+ * live batched plan or server still uses.  NULL is accepted and ignored. */
 bf_status bf_destroy(bf_filter *f);
 
 /* Bulk construction: adds keys[0..n) (device pointer).  n = 0 is a no-op.
@@ -181,8 +194,7 @@ bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
  * choice resolved by the measured crossover (partitioned from about 1.5 M
  * keys + filter bytes / 80; for the classic layout n counts k records per
  * key).  For callers that plan workspace memory (17-21 bytes per key for a
- * partitioned add) or stream ordering (a partitioned add owns its filter
- * while it runs).  Host only: enqueues nothing and touches no device.
+ * partitioned add).  Host only: enqueues nothing and touches no device.
  * BF_EINVAL if f or out is NULL. */
 bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
 

@@ -186,6 +186,85 @@ bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
+// How a call touches the words, for the stream order of FilterOrder.
+enum class Access {
+  kUse,     // reads the words, or writes them in a way the caller orders (clear, import)
+  kDirect,  // atomic OR of pattern words: commutes with other direct adds
+  kOwner,   // partitioned add: loads whole chunks and stores them back
+};
+
+hipEvent_t new_event() {
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Runs `enqueue` (which enqueues one call's work on `stream`) in the stream
+// order of the filter: waits first as `access` requires, then records the
+// filter's last use on `stream`.  The filter's lock is held throughout, so
+// the order decided here is the order enqueued.  Work captured into a HIP
+// graph is ordered by the capturing caller instead (events recorded outside
+// a capture cannot be waited on inside it).
+template <class F>
+bf_status ordered_call(bf_filter* f, hipStream_t stream, Access access, F&& enqueue) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    cap = hipStreamCaptureStatusNone;
+  }
+  if (cap != hipStreamCaptureStatusNone) return enqueue();
+  FilterOrder& o = f->order;
+  std::lock_guard<std::mutex> lk(o.mu);
+  if (access == Access::kOwner) {
+    for (const StreamMark& m : o.marks)
+      if (m.stream != stream && hipStreamWaitEvent(stream, m.event, 0) != hipSuccess)
+        return BF_EDEVICE;
+  } else if (access == Access::kDirect && o.part_pending) {
+    if (hipStreamWaitEvent(stream, o.part_event, 0) != hipSuccess) return BF_EDEVICE;
+  }
+  const bf_status st = enqueue();
+  if (st != BF_OK) return st;
+  hipEvent_t ev = nullptr;
+  for (const StreamMark& m : o.marks)
+    if (m.stream == stream) ev = m.event;
+  if (ev == nullptr) {
+    ev = new_event();
+    if (ev == nullptr) return BF_EDEVICE;
+    o.marks.push_back(StreamMark{stream, ev});
+  }
+  if (hipEventRecord(ev, stream) != hipSuccess) return BF_EDEVICE;
+  if (access == Access::kOwner) {
+    if (o.part_event == nullptr && (o.part_event = new_event()) == nullptr) return BF_EDEVICE;
+    if (hipEventRecord(o.part_event, stream) != hipSuccess) return BF_EDEVICE;
+    o.part_pending = true;
+    // every other stream's last use is ordered before this add: its mark
+    // on `stream` stands for them from now on
+    for (const StreamMark& m : o.marks)
+      if (m.stream != stream) (void)hipEventDestroy(m.event);
+    o.marks.assign(1, StreamMark{stream, ev});
+  }
+  return BF_OK;
+}
+
+// Waits for the filter's last use on every stream and releases its events.
+bf_status drain_filter(bf_filter* f) {
+  FilterOrder& o = f->order;
+  std::lock_guard<std::mutex> lk(o.mu);
+  bf_status st = BF_OK;
+  for (const StreamMark& m : o.marks) {
+    if (hipEventSynchronize(m.event) != hipSuccess) st = BF_EDEVICE;
+    (void)hipEventDestroy(m.event);
+  }
+  o.marks.clear();
+  if (o.part_event != nullptr) (void)hipEventDestroy(o.part_event);
+  o.part_event = nullptr;
+  o.part_pending = false;
+  return st;
+}
+
 }  // namespace
 
 bf_status bfhip::alloc_filter_words(bf_filter* f) {
@@ -286,8 +365,7 @@ bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t w
 
 bf_status bf_destroy(bf_filter* f) {
   if (f == nullptr) return BF_OK;
-  bf_status st = BF_OK;
-  if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
+  bf_status st = drain_filter(f);
   if (f->owns_words && hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
   delete f;
   return st;
@@ -297,7 +375,9 @@ bf_status bf_add(bf_filter* f, const uint64_t* d_keys, uint64_t n, void* stream)
   if (f == nullptr) return BF_EINVAL;
   if (n == 0) return BF_OK;
   if (d_keys == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0) return BF_EINVAL;
-  return launch(f, BF_OP_ADD, d_keys, n, nullptr, stream);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Access access = add_partitions(f, n) ? Access::kOwner : Access::kDirect;
+  return ordered_call(f, s, access, [&] { return launch(f, BF_OP_ADD, d_keys, n, nullptr, stream); });
 }
 
 bf_status bf_contains(const bf_filter* f, const uint64_t* d_keys, uint64_t n, uint8_t* d_out,
@@ -306,28 +386,36 @@ bf_status bf_contains(const bf_filter* f, const uint64_t* d_keys, uint64_t n, ui
   if (n == 0) return BF_OK;
   if (d_keys == nullptr || d_out == nullptr || reinterpret_cast<uintptr_t>(d_keys) % 8 != 0)
     return BF_EINVAL;
-  return launch(const_cast<bf_filter*>(f), BF_OP_CONTAINS, d_keys, n, d_out, stream);
+  bf_filter* g = const_cast<bf_filter*>(f);
+  return ordered_call(g, static_cast<hipStream_t>(stream), Access::kUse,
+                      [&] { return launch(g, BF_OP_CONTAINS, d_keys, n, d_out, stream); });
 }
 
 bf_status bf_clear(bf_filter* f, void* stream) {
   if (f == nullptr) return BF_EINVAL;
-  return clear_words(f->d_words, f->nbytes, static_cast<hipStream_t>(stream));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return ordered_call(f, s, Access::kUse, [&] { return clear_words(f->d_words, f->nbytes, s); });
 }
 
 bf_status bf_export_words(const bf_filter* f, void* dst, uint64_t nbytes, void* stream) {
   if (f == nullptr || dst == nullptr || nbytes < f->nbytes) return BF_EINVAL;
-  if (hipMemcpyAsync(dst, f->d_words, f->nbytes, hipMemcpyDefault,
-                     static_cast<hipStream_t>(stream)) != hipSuccess)
-    return BF_EDEVICE;
-  return BF_OK;
+  bf_filter* g = const_cast<bf_filter*>(f);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return ordered_call(g, s, Access::kUse, [&] {
+    return hipMemcpyAsync(dst, g->d_words, g->nbytes, hipMemcpyDefault, s) == hipSuccess
+               ? BF_OK
+               : BF_EDEVICE;
+  });
 }
 
 bf_status bf_import_words(bf_filter* f, const void* src, uint64_t nbytes, void* stream) {
   if (f == nullptr || src == nullptr || nbytes != f->nbytes) return BF_EINVAL;
-  if (hipMemcpyAsync(f->d_words, src, f->nbytes, hipMemcpyDefault,
-                     static_cast<hipStream_t>(stream)) != hipSuccess)
-    return BF_EDEVICE;
-  return BF_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return ordered_call(f, s, Access::kUse, [&] {
+    return hipMemcpyAsync(f->d_words, src, f->nbytes, hipMemcpyDefault, s) == hipSuccess
+               ? BF_OK
+               : BF_EDEVICE;
+  });
 }
 
 bf_status bf_info(const bf_filter* f, bf_info_t* out) {

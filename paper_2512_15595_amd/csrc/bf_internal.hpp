@@ -5,7 +5,30 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <vector>
+
 #include "../../include/bf.h"
+
+namespace bfhip {
+// Stream order of the bf.h calls on one filter (bf_api.hip: ordered_call).
+// Every call records the filter's last use on its stream.  A partitioned add
+// loads whole chunks into LDS and stores them back, so it first waits for
+// every earlier call on every stream, and a direct add (atomic OR into the
+// words) waits for the last partitioned add: adds from any streams then
+// commute under every strategy, as OR does.  bf_destroy waits for the last
+// uses of its filter only.
+struct StreamMark {
+  hipStream_t stream;
+  hipEvent_t event;
+};
+struct FilterOrder {
+  std::mutex mu;
+  std::vector<StreamMark> marks;      // last use per stream
+  hipEvent_t part_event = nullptr;    // recorded after the last partitioned add
+  bool part_pending = false;
+};
+}  // namespace bfhip
 
 struct bf_filter {
   uint64_t num_blocks;
@@ -21,6 +44,7 @@ struct bf_filter {
   bool owns_words;          // false for bf_create_in
   uint32_t groups;          // cache-sectorized z, else 0
   uint64_t num_bits;        // nbytes * 8
+  bfhip::FilterOrder order;
 };
 
 namespace bfhip {

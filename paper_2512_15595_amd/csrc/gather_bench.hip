@@ -83,45 +83,72 @@ __global__ __launch_bounds__(kThreads) void random_read_kernel(const uint8_t* bu
   if (acc == 0x9e3779b9u) sink[0] = acc;  // practically never; keeps the loads
 }
 
-// 16-byte load with an explicit cache policy: 1 = nontemporal hint,
-// 2 = sc1 (system coherence scope), 3 = sc0 sc1, 4 = nt sc1.
+// Eight independent 16-byte loads with an explicit cache policy, all issued
+// before one wait in the same asm block (so the eight are in flight
+// together, as the compiler keeps the plain loads of random_read_kernel):
+// 2 = sc1 (system coherence scope), 3 = sc0 sc1, 4 = nt sc1.  Outputs are
+// early-clobber, so no load overwrites an address another load still needs.
+#define BFB_LOAD8_POLICY(FLAGS)                                                  \
+  asm volatile("global_load_dwordx4 %0, %8, off " FLAGS "\n\t"                   \
+               "global_load_dwordx4 %1, %9, off " FLAGS "\n\t"                   \
+               "global_load_dwordx4 %2, %10, off " FLAGS "\n\t"                  \
+               "global_load_dwordx4 %3, %11, off " FLAGS "\n\t"                  \
+               "global_load_dwordx4 %4, %12, off " FLAGS "\n\t"                  \
+               "global_load_dwordx4 %5, %13, off " FLAGS "\n\t"                  \
+               "global_load_dwordx4 %6, %14, off " FLAGS "\n\t"                  \
+               "global_load_dwordx4 %7, %15, off " FLAGS "\n\t"                  \
+               "s_waitcnt vmcnt(0)"                                              \
+               : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), \
+                 "=&v"(v[5]), "=&v"(v[6]), "=&v"(v[7])                           \
+               : "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), \
+                 "v"(p[6]), "v"(p[7])                                            \
+               : "memory")
+
+// 1 = nontemporal hint (the compiler's own loads, scheduled freely).
 template <int POL>
-__device__ __forceinline__ u32x4 load16_policy(const uint8_t* p) {
+__device__ __forceinline__ void load8_policy(const uint8_t* const (&p)[8], u32x4 (&v)[8]) {
   if constexpr (POL == 1) {
-    return __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(p[i]));
+  } else if constexpr (POL == 2) {
+    BFB_LOAD8_POLICY("sc1");
+  } else if constexpr (POL == 3) {
+    BFB_LOAD8_POLICY("sc0 sc1");
   } else {
-    u32x4 v;
-    if constexpr (POL == 2)
-      asm volatile("global_load_dwordx4 %0, %1, off sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
-    else if constexpr (POL == 3)
-      asm volatile("global_load_dwordx4 %0, %1, off sc0 sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
-    else
-      asm volatile("global_load_dwordx4 %0, %1, off nt sc1\n\ts_waitcnt vmcnt(0)" : "=v"(v) : "v"(p) : "memory");
-    return v;
+    BFB_LOAD8_POLICY("nt sc1");
   }
 }
 
-// Random SEG-byte reads (one lane per segment) with cache policy POL.
+// Random SEG-byte reads (one lane per segment) with cache policy POL: the
+// thread's kAccessPerThread segments are read as 16-byte pieces, eight
+// pieces in flight at a time.  An access past n_access reads segment 0 (in
+// bounds; its value only feeds the sink test).
 template <int SEG, int POL>
 __global__ __launch_bounds__(kThreads) void random_read_policy_kernel(const uint8_t* buf,
                                                                       uint64_t n_access,
                                                                       uint32_t nseg_lo,
                                                                       uint32_t nseg_hi_mask,
                                                                       uint32_t seed, uint32_t* sink) {
+  static_assert(SEG % 16 == 0 && (kAccessPerThread * SEG / 16) % 8 == 0, "whole groups of 8 pieces");
   const uint64_t tid = static_cast<uint64_t>(blockIdx.x) * kThreads + threadIdx.x;
   const uint64_t threads = static_cast<uint64_t>(gridDim.x) * kThreads;
-  uint32_t acc = 0;
+  const uint8_t* base[kAccessPerThread];
 #pragma unroll
   for (int r = 0; r < kAccessPerThread; ++r) {
     const uint64_t a = tid + static_cast<uint64_t>(r) * threads;
-    if (a < n_access) {
-      const uint64_t seg = segment_of(a, seed, nseg_lo, nseg_hi_mask);
+    base[r] = buf + (a < n_access ? segment_of(a, seed, nseg_lo, nseg_hi_mask) : 0) * SEG;
+  }
+  constexpr int kPieces = SEG / 16;
+  uint32_t acc = 0;
 #pragma unroll
-      for (int i = 0; i < SEG / 16; ++i) {
-        u32x4 v = load16_policy<POL>(buf + seg * SEG + 16 * i);
-        acc ^= v.x ^ v.y ^ v.z ^ v.w;
-      }
-    }
+  for (int g = 0; g < kAccessPerThread * kPieces / 8; ++g) {
+    const uint8_t* p[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) p[i] = base[(g * 8 + i) / kPieces] + 16 * ((g * 8 + i) % kPieces);
+    u32x4 v[8];
+    load8_policy<POL>(p, v);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc ^= v[i].x ^ v[i].y ^ v[i].z ^ v[i].w;
   }
   if (acc == 0x9e3779b9u) sink[0] = acc;
 }

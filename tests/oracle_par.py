@@ -1,0 +1,92 @@
+"""Runs the unchanged single-threaded CPU oracle over many host threads, for
+parity checks at full size.
+
+Nothing here computes a hash, a block or a pattern: every filter byte and
+every lookup result comes from one call of the oracle's own C functions.
+The work is split so that the calls touch disjoint outputs:
+
+* the words of a filter are built block range by block range
+  (``oracle.block_words`` over a contiguous range of blocks, which applies
+  exactly the keys that select a block of the range), and the ranges are
+  concatenated;
+* lookups are split into query slices, each answered by
+  ``OracleFilter.contains`` semantics over the complete oracle words.
+
+ctypes releases the GIL for the duration of each C call, so the threads run
+in parallel.  OR is commutative and idempotent, so the merged result is the
+one a single call over all keys gives (tests/test_oracle.py pins the
+block-range form against the whole-filter form on small filters).
+"""
+from __future__ import annotations
+
+import concurrent.futures
+import os
+
+import numpy as np
+
+import oracle
+
+
+def workers(limit: int = 16) -> int:
+    """Threads to use: the CPUs this process may run on, at most `limit`."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 4
+    return max(1, min(n, limit))
+
+
+def _ranges(total: int, parts: int):
+    parts = max(1, min(parts, total)) if total > 0 else 1
+    step = -(-total // parts)
+    return [(lo, min(total, lo + step)) for lo in range(0, total, step)] or [(0, 0)]
+
+
+def filter_words(num_blocks: int, words_per_block: int, word_bits: int, k: int, seed: int,
+                 keys: np.ndarray, threads: int | None = None, parts: int | None = None) -> np.ndarray:
+    """The oracle's filter bytes after adding `keys`, built by block ranges."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    block_bytes = words_per_block * word_bits // 8
+    out = np.zeros(num_blocks * block_bytes, dtype=np.uint8)
+    threads = threads or workers()
+    ranges = _ranges(num_blocks, parts or threads)
+
+    def one(r):
+        lo, hi = r
+        if hi <= lo:
+            return
+        sel = np.arange(lo, hi, dtype=np.uint64)
+        rows = oracle.block_words(num_blocks, words_per_block, word_bits, k, seed, keys, sel)
+        out[lo * block_bytes:hi * block_bytes] = rows.reshape(-1)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, ranges))
+    return out
+
+
+def contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, word_bits: int,
+             k: int, seed: int, queries: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """The oracle's lookup result of every query against `filter_bytes`
+    (oracle words), by query slices."""
+    queries = np.ascontiguousarray(queries, dtype=np.uint64)
+    out = np.zeros(queries.size, dtype=np.uint8)
+    threads = threads or workers()
+    view = oracle.OracleFilter(num_blocks, words_per_block, word_bits, k, seed)
+    assert filter_bytes.size == view.nbytes
+    view.bytes = filter_bytes  # the zero state it allocated is never touched
+
+    def one(r):
+        lo, hi = r
+        if hi > lo:
+            out[lo:hi] = view.contains(queries[lo:hi])
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, _ranges(queries.size, 4 * threads)))
+    return out
+
+
+def per_filter(jobs, fn, threads: int | None = None):
+    """fn(job) for every job on a thread pool, results in job order (used to
+    run one independent oracle filter per job)."""
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads or workers()) as ex:
+        return list(ex.map(fn, jobs))

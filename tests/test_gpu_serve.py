@@ -164,3 +164,81 @@ def test_oversized_request_is_refused():
     finally:
         srv.close()
         f.close()
+
+
+def _dense_scenario(nfilters=8, nreq=48, seed=31):
+    """Served mix whose adds take the partitioned construction: 4-16 MiB
+    filters, adds of 2-4 M keys (above the automatic crossover of about
+    1.5 M keys + bytes / 80), lookups of 10^3 - 2 * 10^6 keys, one add per
+    three requests, all arriving within a few hundred microseconds."""
+    g = workloads.rng(seed)
+    block = 32
+    sizes = workloads.log_uniform_sizes(nfilters, 4 << 20, 16 << 20, block, seed + 1)
+    params = [dict(num_blocks=int(sz) // block, words_per_block=8, word_bits=32, k=8, seed=700 + i)
+              for i, sz in enumerate(sizes)]
+    prepop = [workloads.splitmix64(1900 + i, 0, int(sz) // 4) for i, sz in enumerate(sizes)]
+    ops = np.where(g.random(nreq) < 1 / 3, 0, 1)
+    filt = g.integers(0, nfilters, size=nreq)
+    lo_hi = np.where(ops == 0, 2e6, 1e3), np.where(ops == 0, 4e6, 2e6)
+    ns = np.exp(np.log(lo_hi[0]) + g.random(nreq) * (np.log(lo_hi[1]) - np.log(lo_hi[0]))).astype(np.int64)
+    keys, starts = [], [0]
+    for i in range(nreq):
+        f = int(filt[i])
+        if ops[i] == 0:
+            kk = workloads.splitmix64(15000 + i, 0, int(ns[i]))
+        else:
+            kk = workloads.mixed_queries(int(ns[i]), 1900 + f, 0, prepop[f].size, 17000 + i, 0, 0.5,
+                                         18000 + i)
+        keys.append(kk)
+        starts.append(starts[-1] + int(ns[i]))
+    arrivals = np.cumsum(g.exponential(5_000, size=nreq)).astype(np.int64)
+    return params, prepop, ops, filt, ns, np.concatenate(keys), np.array(starts), arrivals
+
+
+def _expected_by_filter(params, prepop, ops, filt, ns, keys, starts):
+    """The sequential oracle replay, one host thread per filter (filters are
+    independent; each replays its own requests in submission order)."""
+    import oracle_par
+
+    out = np.zeros(keys.size, dtype=np.uint8)
+
+    def replay(j):
+        r = oracle.OracleFilter(**params[j])
+        r.add(prepop[j])
+        for i in np.flatnonzero(filt == j):
+            a, b = starts[i], starts[i + 1]
+            if ops[i] == 0:
+                r.add(keys[a:b])
+            else:
+                out[a:b] = r.contains(keys[a:b])
+        return r.bytes
+
+    words = oracle_par.per_filter(list(range(len(params))), replay)
+    return words, out
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("cfg", [dict(), dict(nstreams=3, max_inflight=4)], ids=["default", "few_slots"])
+def test_served_partitioned_adds_equal_sequential_oracle(cfg):
+    bf = _bf()
+    sc = _dense_scenario()
+    params, prepop, ops, filt, ns, keys, starts, arrivals = sc
+    # every served add takes the partitioned construction (host-only query)
+    probes = [bf.BloomFilter(**p) for p in params]
+    try:
+        for i in np.flatnonzero(ops == 0):
+            assert probes[int(filt[i])].add_strategy(int(ns[i])) == bf.BF_STRATEGY_PARTITIONED
+    finally:
+        for pr in probes:
+            pr.close()
+    log(f"serve dense cfg={cfg}: {len(ops)} requests ({int((ops == 0).sum())} partitioned adds), "
+        f"{keys.size} keys")
+    want_words, want_out = _expected_by_filter(params, prepop, ops, filt, ns, keys, starts)
+    res, stats, out, words = _run(*sc, serial=False, **cfg)
+    assert all(r.status == 0 for r in res)
+    mask = np.repeat(ops == 1, ns)
+    assert np.array_equal(out[mask], want_out[mask])
+    for i in range(len(params)):
+        assert np.array_equal(words[i], want_words[i]), i
+    # requests overlapped on the device
+    assert stats.peak_inflight_launches > 1
