@@ -1,5 +1,6 @@
-"""Runs the unchanged single-threaded CPU oracle over many host threads, for
-parity checks at full size.
+"""Runs the unchanged single-threaded CPU oracle over many host threads --
+TEST INFRASTRUCTURE, like the rest of this package: for parity checks at
+full size and for the all-core timing of the oracle beside the benchmark.
 
 Nothing here computes a hash, a block or a pattern: every filter byte and
 every lookup result comes from one call of the oracle's own C functions.
@@ -24,7 +25,7 @@ import os
 
 import numpy as np
 
-import oracle
+from . import OracleFilter, block_words
 
 
 def workers(limit: int = 16) -> int:
@@ -56,7 +57,7 @@ def filter_words(num_blocks: int, words_per_block: int, word_bits: int, k: int, 
         if hi <= lo:
             return
         sel = np.arange(lo, hi, dtype=np.uint64)
-        rows = oracle.block_words(num_blocks, words_per_block, word_bits, k, seed, keys, sel)
+        rows = block_words(num_blocks, words_per_block, word_bits, k, seed, keys, sel)
         out[lo * block_bytes:hi * block_bytes] = rows.reshape(-1)
 
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
@@ -71,7 +72,7 @@ def contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, wo
     queries = np.ascontiguousarray(queries, dtype=np.uint64)
     out = np.zeros(queries.size, dtype=np.uint8)
     threads = threads or workers()
-    view = oracle.OracleFilter(num_blocks, words_per_block, word_bits, k, seed)
+    view = OracleFilter(num_blocks, words_per_block, word_bits, k, seed)
     assert filter_bytes.size == view.nbytes
     view.bytes = filter_bytes  # the zero state it allocated is never touched
 

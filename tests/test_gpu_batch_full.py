@@ -19,7 +19,7 @@ import pytest
 import torch
 
 import oracle
-import oracle_par
+from oracle import parallel as oracle_par
 from gpu_helpers import log
 from paper_2512_15595_amd import workloads
 

@@ -5,7 +5,7 @@ benchmark times: a 1 GiB filter (2^25 blocks of 8 x 32-bit words, k = 8),
 Every one of the 2^30 filter bytes and every one of the 3 x 2^28 lookup
 bytes is compared with the CPU oracle.  The oracle is the unchanged
 single-threaded C definition, run on host threads over disjoint block
-ranges (words) and query slices (lookups) by tests/oracle_par.py.  The
+ranges (words) and query slices (lookups) by oracle/parallel.py.  The
 construction the benchmark times (the default strategy, partitioned at this
 density) is compared with the oracle; the paper's direct construction at the
 same size must then give the same words.
@@ -20,7 +20,7 @@ import pytest
 import torch
 
 import fpr_model
-import oracle_par
+from oracle import parallel as oracle_par
 from gpu_helpers import log
 from paper_2512_15595_amd import workloads
 

@@ -198,7 +198,7 @@ def _dense_scenario(nfilters=8, nreq=48, seed=31):
 def _expected_by_filter(params, prepop, ops, filt, ns, keys, starts):
     """The sequential oracle replay, one host thread per filter (filters are
     independent; each replays its own requests in submission order)."""
-    import oracle_par
+    from oracle import parallel as oracle_par
 
     out = np.zeros(keys.size, dtype=np.uint8)
 

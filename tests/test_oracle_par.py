@@ -1,4 +1,4 @@
-"""The threaded driver of the unchanged oracle (tests/oracle_par.py) used by
+"""The threaded driver of the unchanged oracle (oracle/parallel.py) used by
 the full-size parity tests gives exactly what one single-threaded oracle call
 gives, for ragged block ranges and query slices."""
 from __future__ import annotations
@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-import oracle_par
+from oracle import parallel as oracle_par
 from paper_2512_15595_amd import workloads
 
 
