@@ -63,6 +63,8 @@ typedef int32_t bf_status;
 #define BF_ENOMEM (-2)        /* device allocation failed */
 #define BF_EDEVICE (-3)       /* HIP runtime / launch error */
 #define BF_EUNSUPPORTED (-4)  /* valid request this build has no kernel for */
+#define BF_ESCRATCH (-5)      /* bf_add_noalloc: the add needs more workspace than
+                                 BF_NOALLOC_SCRATCH_BYTES; nothing enqueued */
 
 #define BF_OP_ADD 0
 #define BF_OP_CONTAINS 1
@@ -197,6 +199,30 @@ bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
  * partitioned add).  Host only: enqueues nothing and touches no device.
  * BF_EINVAL if f or out is NULL. */
 bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: bf_add with
+ * the same result, whose partitioned construction takes its workspace from
+ * a static device array of BF_NOALLOC_SCRATCH_BYTES instead of the memory
+ * pool.  It calls no hipMalloc, hipFree or other device allocation (the
+ * first call on a device resolves the array's address and creates one
+ * event; a filter's first call on a stream creates that stream's event, as
+ * every bf.h call does).  Each device holds one array, loaded with the
+ * library's code on the first call there and kept until the process ends.
+ * An add the automatic rule builds directly (one atomic OR group per key)
+ * needs no workspace and is bf_add itself.  A partitioned add must fit one
+ * pass of the array (at most 2^28 records; the workspace is about 17-25
+ * bytes per key plus about 650 bytes per 64 KiB chunk of filter, so up to
+ * about 14 M keys into filters of 64 MiB or less and 10 M into a 1 GiB
+ * filter): larger adds give BF_ESCRATCH with nothing enqueued.  Calls on one device
+ * share the array, which keeps the last call's contents (the kernels clear
+ * the counters they need): outside graph capture the library orders them
+ * with one event per device, so they never overlap; calls captured into
+ * graphs are ordered by their caller, and captured calls that overlap on
+ * one device race on the array.  The current device must be the filter's
+ * (else BF_EINVAL). */
+#define BF_NOALLOC_SCRATCH_BYTES (256ull << 20)
+bf_status bf_add_noalloc(bf_filter *f, const uint64_t *d_keys, uint64_t n, void *stream);
 
 /* Static description of a status code. */
 const char *bf_strerror(bf_status s);

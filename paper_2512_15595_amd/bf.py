@@ -29,6 +29,8 @@ BF_EINVAL = -1
 BF_ENOMEM = -2
 BF_EDEVICE = -3
 BF_EUNSUPPORTED = -4
+BF_ESCRATCH = -5
+BF_NOALLOC_SCRATCH_BYTES = 256 << 20
 BF_OP_ADD = 0
 BF_OP_CONTAINS = 1
 BF_STRATEGY_AUTO = 0
@@ -92,6 +94,8 @@ _lib.bf_clear.argtypes = [_vp, _vp]
 _lib.bf_clear.restype = _i32
 _lib.bf_info.argtypes = [_vp, ctypes.POINTER(bf_info_t)]
 _lib.bf_info.restype = _i32
+_lib.bf_add_noalloc.argtypes = [_vp, _vp, _u64, _vp]
+_lib.bf_add_noalloc.restype = _i32
 _lib.bf_add_strategy.argtypes = [_vp, _u64, ctypes.POINTER(_u32)]
 _lib.bf_add_strategy.restype = _i32
 _lib.bf_set_mapping.argtypes = [_vp, ctypes.c_int, _u32, _u32, _u32]
@@ -251,6 +255,10 @@ def bf_add(f, d_keys: int, n: int, stream: int = 0) -> int:
     return _lib.bf_add(f, d_keys, n, stream)
 
 
+def bf_add_noalloc(f, d_keys: int, n: int, stream: int = 0) -> int:
+    return _lib.bf_add_noalloc(f, d_keys, n, stream)
+
+
 def bf_contains(f, d_keys: int, n: int, d_out: int, stream: int = 0) -> int:
     return _lib.bf_contains(f, d_keys, n, d_out, stream)
 
@@ -378,6 +386,13 @@ class _Filter:
     def add(self, keys, stream=None) -> None:
         keys = self._keys(keys)
         _check(bf_add(self._h, keys.data_ptr(), keys.numel(), _stream_ptr(stream)), "bf_add")
+
+    def add_noalloc(self, keys, stream=None) -> None:
+        """bf_add_noalloc: as add, with no device allocation (a partitioned
+        add uses the library's static scratch array)."""
+        keys = self._keys(keys)
+        _check(bf_add_noalloc(self._h, keys.data_ptr(), keys.numel(), _stream_ptr(stream)),
+               "bf_add_noalloc")
 
     def contains(self, keys, out=None, stream=None):
         import torch

@@ -186,69 +186,6 @@ bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
-// How a call touches the words, for the stream order of FilterOrder.
-enum class Access {
-  kUse,     // reads the words, or writes them in a way the caller orders (clear, import)
-  kDirect,  // atomic OR of pattern words: commutes with other direct adds
-  kOwner,   // partitioned add: loads whole chunks and stores them back
-};
-
-hipEvent_t new_event() {
-  hipEvent_t e = nullptr;
-  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  return e;
-}
-
-// Runs `enqueue` (which enqueues one call's work on `stream`) in the stream
-// order of the filter: waits first as `access` requires, then records the
-// filter's last use on `stream`.  The filter's lock is held throughout, so
-// the order decided here is the order enqueued.  Work captured into a HIP
-// graph is ordered by the capturing caller instead (events recorded outside
-// a capture cannot be waited on inside it).
-template <class F>
-bf_status ordered_call(bf_filter* f, hipStream_t stream, Access access, F&& enqueue) {
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) {
-    (void)hipGetLastError();
-    cap = hipStreamCaptureStatusNone;
-  }
-  if (cap != hipStreamCaptureStatusNone) return enqueue();
-  FilterOrder& o = f->order;
-  std::lock_guard<std::mutex> lk(o.mu);
-  if (access == Access::kOwner) {
-    for (const StreamMark& m : o.marks)
-      if (m.stream != stream && hipStreamWaitEvent(stream, m.event, 0) != hipSuccess)
-        return BF_EDEVICE;
-  } else if (access == Access::kDirect && o.part_pending) {
-    if (hipStreamWaitEvent(stream, o.part_event, 0) != hipSuccess) return BF_EDEVICE;
-  }
-  const bf_status st = enqueue();
-  if (st != BF_OK) return st;
-  hipEvent_t ev = nullptr;
-  for (const StreamMark& m : o.marks)
-    if (m.stream == stream) ev = m.event;
-  if (ev == nullptr) {
-    ev = new_event();
-    if (ev == nullptr) return BF_EDEVICE;
-    o.marks.push_back(StreamMark{stream, ev});
-  }
-  if (hipEventRecord(ev, stream) != hipSuccess) return BF_EDEVICE;
-  if (access == Access::kOwner) {
-    if (o.part_event == nullptr && (o.part_event = new_event()) == nullptr) return BF_EDEVICE;
-    if (hipEventRecord(o.part_event, stream) != hipSuccess) return BF_EDEVICE;
-    o.part_pending = true;
-    // every other stream's last use is ordered before this add: its mark
-    // on `stream` stands for them from now on
-    for (const StreamMark& m : o.marks)
-      if (m.stream != stream) (void)hipEventDestroy(m.event);
-    o.marks.assign(1, StreamMark{stream, ev});
-  }
-  return BF_OK;
-}
-
 // Waits for the filter's last use on every stream and releases its events.
 bf_status drain_filter(bf_filter* f) {
   FilterOrder& o = f->order;
@@ -469,6 +406,7 @@ const char* bf_strerror(bf_status s) {
     case BF_ENOMEM: return "device allocation failed";
     case BF_EDEVICE: return "HIP runtime or launch error";
     case BF_EUNSUPPORTED: return "no kernel for this layout and mapping";
+    case BF_ESCRATCH: return "the add needs more workspace than the static scratch array holds";
     default: return "unknown status";
   }
 }

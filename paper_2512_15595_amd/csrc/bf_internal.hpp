@@ -11,7 +11,7 @@
 #include "../../include/bf.h"
 
 namespace bfhip {
-// Stream order of the bf.h calls on one filter (bf_api.hip: ordered_call).
+// Stream order of the bf.h calls on one filter (ordered_call below).
 // Every call records the filter's last use on its stream.  A partitioned add
 // loads whole chunks into LDS and stores them back, so it first waits for
 // every earlier call on every stream, and a direct add (atomic OR into the
@@ -64,6 +64,11 @@ bool partition_applicable(const bf_filter* f, uint64_t n);
 // if the filter cannot be partitioned).
 uint64_t partition_workspace_bytes(const bf_filter* f, uint64_t n);
 bf_status partitioned_add(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream);
+// One partitioned pass (n keys, at most 2^28 records) over a caller-given
+// workspace of ws_bytes: BF_ESCRATCH if the pass needs more, BF_EINVAL if n
+// needs several passes.  Enqueues the kernels only (no allocation).
+bf_status partitioned_add_in(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream,
+                             void* ws, uint64_t ws_bytes);
 uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits);
 bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L);
 // Switches a one-filter geometry to sliced high-digit buckets;
@@ -87,6 +92,69 @@ bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m);
 // Whether bf_add of n keys on f takes the partitioned construction (the
 // classic layout counts k records per key).
 bool add_partitions(const bf_filter* f, uint64_t n);
+
+// How a call touches the words, for the stream order of FilterOrder.
+enum class Access {
+  kUse,     // reads the words, or writes them in a way the caller orders (clear, import)
+  kDirect,  // atomic OR of pattern words: commutes with other direct adds
+  kOwner,   // partitioned add: loads whole chunks and stores them back
+};
+
+inline hipEvent_t new_event() {
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Runs `enqueue` (which enqueues one call's work on `stream`) in the stream
+// order of the filter: waits first as `access` requires, then records the
+// filter's last use on `stream`.  The filter's lock is held throughout, so
+// the order decided here is the order enqueued.  Work captured into a HIP
+// graph is ordered by the capturing caller instead (events recorded outside
+// a capture cannot be waited on inside it).
+template <class F>
+bf_status ordered_call(bf_filter* f, hipStream_t stream, Access access, F&& enqueue) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) {
+    (void)hipGetLastError();
+    cap = hipStreamCaptureStatusNone;
+  }
+  if (cap != hipStreamCaptureStatusNone) return enqueue();
+  FilterOrder& o = f->order;
+  std::lock_guard<std::mutex> lk(o.mu);
+  if (access == Access::kOwner) {
+    for (const StreamMark& m : o.marks)
+      if (m.stream != stream && hipStreamWaitEvent(stream, m.event, 0) != hipSuccess)
+        return BF_EDEVICE;
+  } else if (access == Access::kDirect && o.part_pending) {
+    if (hipStreamWaitEvent(stream, o.part_event, 0) != hipSuccess) return BF_EDEVICE;
+  }
+  const bf_status st = enqueue();
+  if (st != BF_OK) return st;
+  hipEvent_t ev = nullptr;
+  for (const StreamMark& m : o.marks)
+    if (m.stream == stream) ev = m.event;
+  if (ev == nullptr) {
+    ev = new_event();
+    if (ev == nullptr) return BF_EDEVICE;
+    o.marks.push_back(StreamMark{stream, ev});
+  }
+  if (hipEventRecord(ev, stream) != hipSuccess) return BF_EDEVICE;
+  if (access == Access::kOwner) {
+    if (o.part_event == nullptr && (o.part_event = new_event()) == nullptr) return BF_EDEVICE;
+    if (hipEventRecord(o.part_event, stream) != hipSuccess) return BF_EDEVICE;
+    o.part_pending = true;
+    // every other stream's last use is ordered before this add: its mark
+    // on `stream` stands for them from now on
+    for (const StreamMark& m : o.marks)
+      if (m.stream != stream) (void)hipEventDestroy(m.event);
+    o.marks.assign(1, StreamMark{stream, ev});
+  }
+  return BF_OK;
+}
 
 // The classic and cache-sectorized layouts (bf_variants.hip).
 bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op);

@@ -239,19 +239,13 @@ hipMemPool_t workspace_pool(int device) {
 
 namespace {
 
-bf_status partitioned_pass(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
-  PartArgs a{};
-  PartLayout L{};
-  if (!single_geometry(f, n, a, L)) return BF_EUNSUPPORTED;
+// One pass of a partitioned add over the workspace `ws` (at least L.total
+// bytes of the geometry single_geometry gives for n): sets the arguments and
+// enqueues the kernels.
+bf_status partitioned_pass_in(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream,
+                              PartArgs& a, const PartLayout& L, void* ws) {
   const PartKernels k = part_kernels(f);
   if (k.scatter1 == nullptr) return BF_EUNSUPPORTED;
-  hipMemPool_t pool = workspace_pool(f->device);
-  if (pool == nullptr) return BF_EDEVICE;
-  void* ws = nullptr;
-  if (hipMallocFromPoolAsync(&ws, L.total, pool, stream) != hipSuccess) {
-    (void)hipGetLastError();
-    return BF_ENOMEM;
-  }
   part_bind(a, L, ws);
   a.words = f->d_words;
   a.num_blocks = f->layout == BF_LAYOUT_CLASSIC ? f->num_bits / 32 : f->num_blocks;
@@ -268,12 +262,40 @@ bf_status partitioned_pass(bf_filter* f, const uint64_t* keys, uint64_t n, hipSt
   // the cache-sectorized rule takes the bits per selected word
   a.k = f->layout == BF_LAYOUT_CACHE_SECTORIZED ? f->k / f->groups : f->k;
   a.keys = keys;
-  bf_status st = part_launch(a, L, k, stream);
+  return part_launch(a, L, k, stream);
+}
+
+// One pass with its workspace taken from the device pool and returned at
+// its end, both in stream order.
+bf_status partitioned_pass(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream) {
+  PartArgs a{};
+  PartLayout L{};
+  if (!single_geometry(f, n, a, L)) return BF_EUNSUPPORTED;
+  if (part_kernels(f).scatter1 == nullptr) return BF_EUNSUPPORTED;
+  hipMemPool_t pool = workspace_pool(f->device);
+  if (pool == nullptr) return BF_EDEVICE;
+  void* ws = nullptr;
+  if (hipMallocFromPoolAsync(&ws, L.total, pool, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    return BF_ENOMEM;
+  }
+  bf_status st = partitioned_pass_in(f, keys, n, stream, a, L, ws);
   if (hipFreeAsync(ws, stream) != hipSuccess && st == BF_OK) st = BF_EDEVICE;
   return st;
 }
 
 }  // namespace
+
+bf_status partitioned_add_in(bf_filter* f, const uint64_t* keys, uint64_t n, hipStream_t stream,
+                             void* ws, uint64_t ws_bytes) {
+  const uint64_t per_key = f->layout == BF_LAYOUT_CLASSIC ? f->k : 1;
+  if (n == 0 || n > std::max<uint64_t>((1ull << 28) / per_key, 1)) return BF_EINVAL;
+  PartArgs a{};
+  PartLayout L{};
+  if (!single_geometry(f, n, a, L)) return BF_EUNSUPPORTED;
+  if (L.total > ws_bytes) return BF_ESCRATCH;
+  return partitioned_pass_in(f, keys, n, stream, a, L, ws);
+}
 
 // Passes of at most 2^28 records keep the workspace under ~5.5 GB; each pass
 // after the first reads and writes the touched chunks once more.
