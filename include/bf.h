@@ -27,7 +27,7 @@
  *     one byte (0 or 1) per key.
  *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
  *     Calls enqueue and return; they never synchronize, except bf_create
- *     (which zeroes the new words) and bf_destroy (which frees them).
+ *     (which zeroes the new words and waits for that).
  *   - Arguments are validated before anything is enqueued; on error nothing
  *     is enqueued and the status says why.  Launch failures are BF_EDEVICE.
  *     Faults inside a kernel surface at the caller's next synchronization.
@@ -134,7 +134,8 @@ typedef struct {
  * num_blocks in [1, 2^32]; words_per_block in {1,2,4,8,16}; word_bits in
  * {32, 64}; words_per_block <= k <= 32 (a sectorized block needs at least
  * one bit per word, Sec. II-A-5).  Allocates num_blocks * words_per_block *
- * word_bits / 8 bytes with hipMalloc and zeroes them (synchronously).
+ * word_bits / 8 bytes from the device's filter pool (stream-ordered,
+ * returned to the device when released) and zeroes them before returning.
  * *out receives the handle (unchanged on error). */
 bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block,
                     uint32_t word_bits, uint32_t k, uint64_t seed,
@@ -150,11 +151,17 @@ bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t w
                        uint32_t k, uint64_t seed, void *d_words, uint64_t nbytes,
                        bf_filter **out);
 
-/* Waits until every bf.h call enqueued on this filter (on any stream) has
- * finished -- other filters' work and other streams are not waited for --
- * then frees the words (not for bf_create_in filters, whose words stay the
- * caller's) and the handle.  The caller must not destroy a filter that a
- * live batched plan or server still uses.  NULL is accepted and ignored. */
+/* Releases the words behind every bf.h call enqueued on this filter, on any
+ * stream, and frees the handle.  The words come from a per-device
+ * stream-ordered pool and are released on a library stream that waits for
+ * the filter's last uses, so the host returns at once and neither other
+ * filters' work nor other streams are waited for (should the pool be
+ * unavailable, the words are a plain allocation: bf_destroy then waits for
+ * the filter's calls on the host before hipFree, which itself waits for the
+ * device).  bf_create_in words stay the caller's: bf_destroy waits on the
+ * host for the filter's calls and does not free them.  The caller must not
+ * destroy a filter that a live batched plan or server still uses.  NULL is
+ * accepted and ignored. */
 bf_status bf_destroy(bf_filter *f);
 
 /* Bulk construction: adds keys[0..n) (device pointer).  n = 0 is a no-op.

@@ -2,6 +2,7 @@
 // mapping selection and kernel launch.
 #include <hip/hip_runtime.h>
 
+#include <map>
 #include <mutex>
 #include <new>
 
@@ -186,13 +187,17 @@ bf_status clear_words(void* p, uint64_t nbytes, hipStream_t stream) {
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
-// Waits for the filter's last use on every stream and releases its events.
-bf_status drain_filter(bf_filter* f) {
+// Releases the filter's events after either waiting for its last use on
+// every stream on the host (wait_stream == nullptr) or making wait_stream
+// wait for them.
+bf_status drain_filter(bf_filter* f, hipStream_t wait_stream) {
   FilterOrder& o = f->order;
   std::lock_guard<std::mutex> lk(o.mu);
   bf_status st = BF_OK;
   for (const StreamMark& m : o.marks) {
-    if (hipEventSynchronize(m.event) != hipSuccess) st = BF_EDEVICE;
+    const hipError_t e = wait_stream != nullptr ? hipStreamWaitEvent(wait_stream, m.event, 0)
+                                                : hipEventSynchronize(m.event);
+    if (e != hipSuccess) st = BF_EDEVICE;
     (void)hipEventDestroy(m.event);
   }
   o.marks.clear();
@@ -204,6 +209,50 @@ bf_status drain_filter(bf_filter* f) {
 
 }  // namespace
 
+namespace {
+
+// Per device: a memory pool for filter words and a library stream on which
+// words are allocated, zeroed and released.  Pool memory is released in
+// stream order (hipFreeAsync), so destroying a filter waits for nothing but
+// that filter's own calls; hipFree would wait for every stream of the
+// device.  The pool returns freed memory to the device at the next
+// synchronization (release threshold 0).
+struct WordsHome {
+  hipMemPool_t pool = nullptr;
+  hipStream_t stream = nullptr;
+};
+std::mutex g_home_mu;
+std::map<int, WordsHome> g_homes;
+
+WordsHome words_home(int device) {
+  std::lock_guard<std::mutex> lk(g_home_mu);
+  WordsHome& h = g_homes[device];
+  if (h.stream == nullptr) {
+    hipMemPoolProps props{};
+    props.allocType = hipMemAllocationTypePinned;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = device;
+    hipMemPool_t pool = nullptr;
+    hipStream_t stream = nullptr;
+    if (hipMemPoolCreate(&pool, &props) != hipSuccess) {
+      (void)hipGetLastError();
+      return WordsHome{};
+    }
+    uint64_t keep = 0;
+    (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+      (void)hipGetLastError();
+      (void)hipMemPoolDestroy(pool);
+      return WordsHome{};
+    }
+    h.pool = pool;
+    h.stream = stream;
+  }
+  return h;
+}
+
+}  // namespace
+
 bf_status bfhip::alloc_filter_words(bf_filter* f) {
   f->num_bits = f->nbytes * 8;
   f->owns_words = true;
@@ -211,14 +260,27 @@ bf_status bfhip::alloc_filter_words(bf_filter* f) {
     delete f;
     return BF_EDEVICE;
   }
-  if (hipMalloc(&f->d_words, f->nbytes) != hipSuccess) {
+  const WordsHome home = words_home(f->device);
+  hipStream_t s = home.stream;
+  f->pooled_words = home.pool != nullptr &&
+                    hipMallocFromPoolAsync(&f->d_words, f->nbytes, home.pool, s) == hipSuccess;
+  if (!f->pooled_words) {
+    // no pool on this device: plain allocation, zeroed on the null stream
     (void)hipGetLastError();
-    delete f;
-    return BF_ENOMEM;
+    s = nullptr;
+    if (hipMalloc(&f->d_words, f->nbytes) != hipSuccess) {
+      (void)hipGetLastError();
+      delete f;
+      return BF_ENOMEM;
+    }
   }
-  if (clear_words(f->d_words, f->nbytes, nullptr) != BF_OK ||
-      hipStreamSynchronize(nullptr) != hipSuccess) {
-    (void)hipFree(f->d_words);
+  if (clear_words(f->d_words, f->nbytes, s) != BF_OK || hipStreamSynchronize(s) != hipSuccess) {
+    if (f->pooled_words) {
+      (void)hipFreeAsync(f->d_words, s);
+      (void)hipStreamSynchronize(s);
+    } else {
+      (void)hipFree(f->d_words);
+    }
     delete f;
     return BF_EDEVICE;
   }
@@ -302,8 +364,17 @@ bf_status bf_create_in(uint64_t num_blocks, uint32_t words_per_block, uint32_t w
 
 bf_status bf_destroy(bf_filter* f) {
   if (f == nullptr) return BF_OK;
-  bf_status st = drain_filter(f);
-  if (f->owns_words && hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
+  bf_status st = BF_OK;
+  if (f->owns_words && f->pooled_words) {
+    // released on the library stream behind the filter's last uses; the
+    // host does not wait
+    hipStream_t s = words_home(f->device).stream;
+    st = drain_filter(f, s);
+    if (st == BF_OK && hipFreeAsync(f->d_words, s) != hipSuccess) st = BF_EDEVICE;
+  } else {
+    st = drain_filter(f, nullptr);
+    if (f->owns_words && hipFree(f->d_words) != hipSuccess) st = BF_EDEVICE;
+  }
   delete f;
   return st;
 }

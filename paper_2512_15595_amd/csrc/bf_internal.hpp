@@ -42,6 +42,7 @@ struct bf_filter {
   bf_mapping_t mapping[2];  // as set by the caller; zero fields = default
   uint32_t layout;          // BF_LAYOUT_*
   bool owns_words;          // false for bf_create_in
+  bool pooled_words;        // words from the device's filter pool (freed in stream order)
   uint32_t groups;          // cache-sectorized z, else 0
   uint64_t num_bits;        // nbytes * 8
   bfhip::FilterOrder order;

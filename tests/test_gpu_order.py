@@ -121,17 +121,18 @@ def test_destroy_waits_for_its_own_filter_only():
     torch.cuda.synchronize()
     log("destroy: long work on filter A (stream 1), filter B destroyed with its work queued (stream 2)")
     fa.add(dka, stream=s1)
-    for _ in range(4):
+    for _ in range(12):                          # ~10 ms of lookups
         fa.contains(dqa, out=out_a, stream=s1)
     done_a = torch.cuda.Event()
     done_a.record(s1)
     fb.add(dkb, stream=s2)
     fb.contains(dqb, out=out_b, stream=s2)
-    fb.close()                                   # waits for B's calls only
+    fb.close()             # releases B's words behind B's calls; no host wait
     a_pending_after_destroy = not done_a.query()
     log(f"destroy: filter A's work still pending when bf_destroy(B) returned: "
         f"{a_pending_after_destroy}")
     torch.cuda.synchronize()
+    assert a_pending_after_destroy, "bf_destroy waited for another filter's work"
     got_a, got_b = out_a.cpu().numpy(), out_b.cpu().numpy()
     fa.close()
     ref_b = oracle.OracleFilter(NB, S_WORDS, WBITS, K, 6)
@@ -166,3 +167,23 @@ def test_destroy_of_an_idle_filter_and_null_stream_use():
     ref.add(workloads.uniform_keys(1000, 9))
     assert np.array_equal(g.words().cpu().numpy(), ref.bytes)
     g.close()
+
+
+def test_destroyed_words_return_to_the_device():
+    """Filter words come from a stream-ordered pool that gives freed memory
+    back at the next synchronization: creating and destroying 4 GiB filters
+    repeatedly leaves the device's free memory where it was."""
+    bf = _bf()
+    torch.cuda.synchronize()
+    free0, _ = torch.cuda.mem_get_info()
+    keys = _dev(workloads.uniform_keys(1_000_000, 501))
+    for i in range(6):
+        f = bf.BloomFilter((4 << 30) // 32, 8, 32, 8, i)
+        f.add(keys)
+        hits = f.contains(keys)
+        f.close()
+        assert bool(hits.all().item())
+    torch.cuda.synchronize()
+    free1, _ = torch.cuda.mem_get_info()
+    log(f"free memory before {free0 / 2**30:.2f} GiB, after {free1 / 2**30:.2f} GiB")
+    assert free1 >= free0 - (1 << 30)
