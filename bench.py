@@ -8,7 +8,15 @@ One step = clear the filter, add 2^28 uniform uint64 keys, then look up
 words, k = 8, 2^25 blocks).  The value is keys processed per second over the
 whole step (adds + lookups), inputs already resident in HBM.
 
-Prints one JSON line (see the module-level contract in the design doc), e.g.
+Beside it, in the same run: the random-access bounds of this GPU (the
+denominators), a 1 GiB streaming copy, the paper's direct construction
+timed against the atomic-OR bound, a bounded served leg (Poisson requests
+at 0.9x and 2x the serial capacity: served and serial p50 / p99 and their
+throughput ratio), the batched leg (4096 filters, one graph launch per op
+against one plain launch per filter), and the CPU oracle on one core and on
+every core of the host.
+
+Prints one JSON line, e.g.
   python bench.py --steps 20 --warmup 3
 """
 from __future__ import annotations
@@ -127,7 +135,11 @@ def measure_bounds(torch, nbytes: int, seg: int, n_access: int, reps: int = 3) -
     del buf, idx, out
     torch.cuda.empty_cache()
     read_keys = [k for k in res if k.startswith("read_")]
-    write_keys = [k for k in res if k.startswith("atomic_") or k.startswith("gups")]
+    # a direct add is one random atomic-OR group per key: its bound is the
+    # best random atomic-OR rate (8-byte words, or the block's segment
+    # covered by one or several lanes); GUPS (load + store, not atomic) is
+    # reported beside it
+    write_keys = [k for k in res if k.startswith("atomic_")]
     return {
         "rates_g_per_s": {k: round(v, 3) for k, v in res.items()},
         "contains_bound": max(res[k] for k in read_keys),
@@ -174,8 +186,55 @@ def committed_traffic(kernel: str, sample_keys: int):
     return entry.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(adds, queries, params, budget_s: float) -> dict:
-    """The CPU oracle (single thread) on a bounded sample of the workload."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline_all_cores(adds, queries, params, n: int, single_bytes) -> dict:
+    """The same oracle on every host core the process may use (at most 16,
+    the box's share): words built block range by block range and lookups
+    answered slice by slice, one unchanged single-threaded oracle call per
+    thread; the words must equal the single-thread run's."""
+    import numpy as np
+
+    from oracle import parallel
+
+    p = params
+    threads = parallel.workers()
+    t0 = time.perf_counter()
+    words = parallel.filter_words(p["num_blocks"], p["words_per_block"], p["word_bits"], p["k"],
+                                  p["seed"], adds[:n], threads=threads)
+    t_add = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    r = parallel.contains(words, p["num_blocks"], p["words_per_block"], p["word_bits"], p["k"],
+                          p["seed"], queries[:n], threads=threads)
+    t_contains = time.perf_counter() - t0
+    same = bool(np.array_equal(words, single_bytes)) if single_bytes is not None else None
+    return {
+        "value": round(2 * n / (t_add + t_contains) / 1e9, 6),
+        "unit": "Gkeys/s",
+        "cores": threads,
+        "kind": "oracle",
+        "cpu_model": cpu_model(),
+        "sample": (f"{n} adds then {n} lookups (50% hits) on the full 1 GiB filter in host memory, "
+                   f"{threads} threads; add {n / t_add / 1e6:.2f} Mkeys/s, contains "
+                   f"{n / t_contains / 1e6:.2f} Mkeys/s, {int(np.sum(r))} positives"),
+        "words_equal_single_thread": same,
+    }
+
+
+def cpu_baseline(adds, queries, params, budget_s: float, keep_words: bool = False):
+    """The CPU oracle (single thread) on a bounded sample of the workload.
+    Returns the summary, the sample size and (keep_words) the oracle bytes."""
     import numpy as np
 
     import oracle
@@ -197,16 +256,18 @@ def cpu_baseline(adds, queries, params, budget_s: float) -> dict:
     t0 = time.perf_counter()
     r = ref.contains(queries[:n])
     t_contains = time.perf_counter() - t0
+    words = ref.bytes if keep_words else None
     del ref
     return {
         "value": round(2 * n / (t_add + t_contains) / 1e9, 6),
         "unit": "Gkeys/s",
         "cores": 1,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": (f"{n} adds then {n} lookups (50% hits) on the full 1 GiB filter in host memory; "
                    f"add {n / t_add / 1e6:.2f} Mkeys/s, contains {n / t_contains / 1e6:.2f} Mkeys/s, "
                    f"{int(np.sum(r))} positives"),
-    }
+    }, n, words
 
 
 def run_batched(args) -> dict:
@@ -871,12 +932,18 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget-s", type=float, default=12.0)
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run one 1 GiB streaming copy (byte-counter calibration)")
+                    help="(the 1 GiB streaming copy now runs by default; kept for old commands)")
+    ap.add_argument("--no-copy", action="store_true", help="skip the 1 GiB streaming copy")
+    ap.add_argument("--no-direct-add", action="store_true", help="skip the direct-construction timing")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--line-serve-requests", type=int, default=2000,
+                    help="requests per load in the served leg of the benchmark line")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no "
-              "multi-GPU path (see the sharding notes in DESIGN.md); use --gpus 1.",
+        print("bench.py measures one GPU: this library runs on a single MI355X and has no "
+              "multi-GPU path; use --gpus 1.",
               file=sys.stderr)
         return 2
 
@@ -884,7 +951,8 @@ def main() -> int:
     import torch
 
     from paper_2512_15595_amd import workloads
-    from paper_2512_15595_amd.bf import BF_OP_ADD, BF_OP_CONTAINS, BF_STRATEGY_PARTITIONED, BloomFilter
+    from paper_2512_15595_amd.bf import (BF_OP_ADD, BF_OP_CONTAINS, BF_STRATEGY_DIRECT,
+                                         BF_STRATEGY_PARTITIONED, BloomFilter)
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
@@ -929,7 +997,7 @@ def main() -> int:
         log(f"[bench] bounds: {bounds}")
 
     copy_gbs = None
-    if args.calibrate_copy:
+    if not args.no_copy:
         copy_gbs = streaming_copy(torch, 1 << 30)
         log(f"[bench] streaming copy of 1 GiB: {copy_gbs:.0f} GB/s (read + write)")
 
@@ -986,6 +1054,25 @@ def main() -> int:
     torch.cuda.synchronize()
     assert found == n, f"false negatives: {n - found}"
 
+    # the paper's construction, one atomic-OR group per key (Sec. IV), timed
+    # on its own after the steps: a cleared filter, the same keys
+    direct_ms = None
+    if not args.no_direct_add:
+        g = BloomFilter(num_blocks, s, S, k, 0)
+        g.set_mapping(BF_OP_ADD, strategy=BF_STRATEGY_DIRECT)
+        dts = []
+        for _ in range(3):
+            g.clear()
+            t = Timer(torch)
+            with t:
+                g.add(d_adds)
+            torch.cuda.synchronize()
+            dts.append(t.ms())
+        direct_ms = float(np.median(dts))
+        direct_same = bool(torch.equal(g.words(), f.words()))
+        g.close()
+        assert direct_same, "direct and partitioned construction differ"
+
     ms = {key: float(np.mean([t.ms() for t in v])) for key, v in times.items()}
     keys_per_step = 4 * n
     ms_per_step = total_ms / args.steps
@@ -1005,18 +1092,31 @@ def main() -> int:
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(achieved / PEAK_HBM_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_key": per_key,
                 "avg_launch_ms": round(dom_ms, 4)}
+    if traffic:
+        # every random block read fetches a whole 128-byte line: what the
+        # memory system moves, against the HBM peak
+        roofline["traffic_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
+        roofline["traffic_frac_of_peak"] = round(traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
 
-    # the add beside it: algorithmic bytes (a random read-modify-write of the
-    # block per key) against the HBM peak; `traffic` is the measured HBM bytes
-    # of the whole add (the three partitioned kernels, or the direct one)
-    add_per_key = 8 + 2 * block_bytes
-    add_achieved = add_per_key * n / (ms["add"] * 1e-3) / 1e9
-    roofline_add = {"bound": "hbm",
+    # the default add: a partitioned construction streams keys, records and
+    # each touched 64 KiB chunk, so its bound is streaming bandwidth; it is
+    # reported by the HBM bytes it moves (counters) against the 1 GiB copy
+    add_traffic = committed_traffic("add", n) if add_partitioned else None
+    roofline_add = {"bound": "hbm", "strategy": "partitioned" if add_partitioned else "direct",
                     "kernels": ("part_scatter1 + part_scatter2 + part_apply" if add_partitioned
                                 else "bf_add_kernel"),
-                    "achieved": round(add_achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                    "frac": round(add_achieved / PEAK_HBM_GBS, 4), "traffic": committed_traffic("add", n),
-                    "algorithmic_bytes_per_key": add_per_key, "avg_launch_ms": round(ms["add"], 4)}
+                    "avg_launch_ms": round(ms["add"], 4), "unit": "GB/s",
+                    "algorithmic_bytes_per_key": 8 + 2 * block_bytes,
+                    "achieved_algorithmic": round((8 + 2 * block_bytes) * n / (ms["add"] * 1e-3) / 1e9, 1),
+                    "traffic": add_traffic}
+    if add_traffic:
+        moved = add_traffic / (ms["add"] * 1e-3) / 1e9
+        roofline_add.update({"traffic_bytes_per_key": round(add_traffic / n, 2),
+                             "achieved_traffic": round(moved, 1), "peak": PEAK_HBM_GBS,
+                             "frac_of_peak": round(moved / PEAK_HBM_GBS, 4)})
+        if copy_gbs:
+            roofline_add.update({"copy_1GiB": round(copy_gbs, 1),
+                                 "frac_of_copy": round(moved / copy_gbs, 4)})
 
     result = {
         "metric": METRIC,
@@ -1045,23 +1145,67 @@ def main() -> int:
         "roofline": roofline,
         "roofline_add": roofline_add,
     }
+    if direct_ms is not None:
+        result["direct_add_gkeys_s"] = round(n / (direct_ms * 1e-3) / 1e9, 3)
+        result["ms"]["direct_add"] = round(direct_ms, 4)
     if copy_gbs is not None:
         result["copy_1GiB_gbs"] = round(copy_gbs, 1)
     if bounds:
         result["random_access_bound"] = bounds
-        result["pct_of_bound"] = {
-            "add": round(100 * add_rate / bounds["add_bound"], 2),
-            "contains": round(100 * contains_rate / bounds["contains_bound"], 2),
-        }
+        pct = {"contains": round(100 * contains_rate / bounds["contains_bound"], 2)}
+        if direct_ms is not None:
+            pct["add_direct"] = round(100 * result["direct_add_gkeys_s"] / bounds["add_bound"], 2)
+        if add_traffic and copy_gbs:
+            pct["add_partitioned_traffic_vs_copy"] = round(100 * roofline_add["frac_of_copy"], 2)
+        result["pct_of_bound"] = pct
     f.close()
     del d_adds, d_q, d_out
     torch.cuda.empty_cache()
 
+    if not args.no_serve:
+        log("[bench] served leg: Poisson requests at 0.9x and 2x the serial capacity")
+        result["served"] = serve_summary(run_serve(argparse.Namespace(
+            **{**vars(args), "serve_requests": args.line_serve_requests, "serve_loads": [0.9, 2.0]})))
+        torch.cuda.empty_cache()
+    if not args.no_batched:
+        log("[bench] batched leg: 4096 filters, graph launch vs one launch per filter")
+        result["batched"] = batched_summary(run_batched(argparse.Namespace(
+            **{**vars(args), "steps": 5, "warmup": 1})))
+        torch.cuda.empty_cache()
+
     if not args.no_cpu_baseline:
-        log("[bench] timing the CPU oracle on a bounded sample")
-        result["cpu_baseline"] = cpu_baseline(adds, queries[50], params, args.cpu_budget_s)
+        log("[bench] timing the CPU oracle on a bounded sample (one core, then all cores)")
+        single, n_cpu, single_words = cpu_baseline(adds, queries[50], params, args.cpu_budget_s,
+                                                   keep_words=True)
+        result["cpu_baseline"] = single
+        result["cpu_baseline_all_cores"] = cpu_baseline_all_cores(adds, queries[50], params, n_cpu,
+                                                                  single_words)
     print(json.dumps(result), flush=True)
     return 0
+
+
+def serve_summary(res: dict) -> dict:
+    """The served leg's figures for the benchmark line."""
+    out = {"workload": res["config"]["workload"], "requests": res["config"]["requests"],
+           "serial_capacity_gkeys_s": res["serial_capacity_gkeys_s"]}
+    for load, r in res["loads"].items():
+        out[f"load_{load}x"] = {
+            "served_gkeys_s": r["served"]["throughput_gkeys_s"],
+            "serial_gkeys_s": r["serial"]["throughput_gkeys_s"],
+            "throughput_ratio": r["throughput_ratio"],
+            "served_p50_ms": r["served"]["p50_ms"], "served_p99_ms": r["served"]["p99_ms"],
+            "serial_p50_ms": r["serial"]["p50_ms"], "serial_p99_ms": r["serial"]["p99_ms"],
+        }
+    return out
+
+
+def batched_summary(res: dict) -> dict:
+    """The batched leg's figures for the benchmark line."""
+    return {"workload": res["config"]["workload"], "gkeys_s": res["value"],
+            "per_filter_gkeys_s": res["plain_per_filter_gkeys_s"],
+            "speedup_vs_per_filter": res["speedup_vs_per_filter"],
+            "add_speedup": res["add_speedup"], "contains_speedup": res["contains_speedup"],
+            "ms": res["ms"], "results_equal": res["results_equal_batched_vs_per_filter"]}
 
 
 if __name__ == "__main__":

@@ -21,8 +21,10 @@
  * graph); the keys of the sparse filters go to the tiled launch, recorded
  * after them, so no sparse filter's words are streamed.  Filter 0's add
  * strategy (bf_set_mapping_ex) can force BF_STRATEGY_DIRECT (tiles only) or
- * BF_STRATEGY_PARTITIONED (every filter partitioned).  The partitioned plan
- * owns its filters while it runs, like a partitioned bf_add.
+ * BF_STRATEGY_PARTITIONED (every filter partitioned).  Launches of a plan
+ * (all three forms) are ordered by the caller against other work on its
+ * filters -- stream order or events; they take no part in the per-filter
+ * stream order of bf.h calls.
  *
  * All filters of a plan must share words_per_block, word_bits and k.  Keys
  * of filter i are d_keys[h_offsets[i] .. h_offsets[i+1]) (device memory,
@@ -76,8 +78,9 @@ bf_status bf_batch_launch(bf_batch *b, void *stream);
  * callers that capture it into graphs of their own). */
 bf_status bf_batch_launch_direct(bf_batch *b, void *stream);
 
-/* The plain alternative the batch replaces: one bf_add / bf_contains launch
- * per filter, in filter order, each with the filter's own mapping. */
+/* The plain alternative the batch replaces: the launch a bf_add /
+ * bf_contains of each filter's keys makes, one per filter, in filter order,
+ * each with the filter's own mapping and strategy. */
 bf_status bf_batch_launch_per_filter(bf_batch *b, void *stream);
 
 bf_status bf_batch_info(const bf_batch *b, bf_batch_info_t *out);

@@ -306,6 +306,15 @@ bool bfhip::add_partitions(const bf_filter* f, uint64_t n) {
   return use_partitioned(f, records, f->mapping[BF_OP_ADD]);
 }
 
+// The work of one bf_add / bf_contains without the filter's stream-order
+// bookkeeping, for batched plans and servers, which order their own launches
+// (bf_batch.h, bf_serve.h).  Arguments are already validated.
+bf_status bfhip::launch_unordered(bf_filter* f, int op, const uint64_t* keys, uint64_t n,
+                                  uint8_t* out, hipStream_t stream) {
+  if (n == 0) return BF_OK;
+  return launch(f, op, keys, n, out, stream);
+}
+
 extern "C" {
 
 bf_status bf_create(uint64_t num_blocks, uint32_t words_per_block, uint32_t word_bits, uint32_t k,

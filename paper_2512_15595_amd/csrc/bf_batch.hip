@@ -468,13 +468,15 @@ bf_status bf_batch_launch_direct(bf_batch* b, void* stream) {
 
 bf_status bf_batch_launch_per_filter(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   for (uint32_t i = 0; i < b->nfilters; ++i) {
     const uint64_t n = b->offsets[i + 1] - b->offsets[i];
     if (n == 0) continue;
     const uint64_t off = b->offsets[i];
     bf_status st = b->op == BF_OP_ADD
-                       ? bf_add(b->filters[i], b->d_keys + off, n, stream)
-                       : bf_contains(b->filters[i], b->d_keys + off, n, b->d_out + off, stream);
+                       ? launch_unordered(b->filters[i], BF_OP_ADD, b->d_keys + off, n, nullptr, s)
+                       : launch_unordered(b->filters[i], BF_OP_CONTAINS, b->d_keys + off, n,
+                                          b->d_out + off, s);
     if (st != BF_OK) return st;
   }
   return BF_OK;

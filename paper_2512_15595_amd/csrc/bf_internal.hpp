@@ -88,6 +88,11 @@ __global__ void part_zero_kernel(unsigned long long* p, uint64_t n);
 // device, d_words (zeroed, synchronously).  On error the handle is freed.
 bf_status alloc_filter_words(bf_filter* f);
 
+// bf_add / bf_contains work without the per-filter stream-order bookkeeping
+// (bf_api.hip), for plans and servers that order their own launches.
+bf_status launch_unordered(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
+                           hipStream_t stream);
+
 // Whether a bulk add of n keys takes the partitioned strategy (bf_api.hip).
 bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m);
 // Whether bf_add of n keys on f takes the partitioned construction (the

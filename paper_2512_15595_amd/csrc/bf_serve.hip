@@ -166,7 +166,8 @@ bool launch_group(bf_server* s, const std::vector<Pending>& group, uint64_t grou
   if (group.size() == 1) {
     const bf_request_t& r = group[0].r;
     bf_filter* f = s->filters[r.filter];
-    st = op == BF_OP_ADD ? bf_add(f, r.d_keys, r.n, sc.s) : bf_contains(f, r.d_keys, r.n, r.d_out, sc.s);
+    // the server orders its filters' work itself (the waits above)
+    st = launch_unordered(f, op, r.d_keys, r.n, op == BF_OP_CONTAINS ? r.d_out : nullptr, sc.s);
   } else {
     if (sc.staged_valid && hipEventSynchronize(sc.staged) != hipSuccess) return false;
     uint64_t ntiles = 0;
@@ -523,8 +524,8 @@ bf_status bf_server_replay_serial(bf_server* s, const bf_request_t* reqs, uint64
     }
     const uint64_t admit = now_ns();
     bf_filter* f = s->filters[r.filter];
-    bf_status rc = r.op == BF_OP_ADD ? bf_add(f, r.d_keys, r.n, st)
-                                     : bf_contains(f, r.d_keys, r.n, r.d_out, st);
+    bf_status rc = launch_unordered(f, static_cast<int>(r.op), r.d_keys, r.n,
+                                    r.op == BF_OP_CONTAINS ? r.d_out : nullptr, st);
     if (rc == BF_OK && hipStreamSynchronize(st) != hipSuccess) rc = BF_EDEVICE;
     results[i] = bf_request_result_t{r.arrival_ns, admit - start, now_ns() - start,
                                      static_cast<uint32_t>(i), rc};
