@@ -87,7 +87,7 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *                   words into one 64-bit atomic OR (needs Phi >= 2); 32 or
  *                   0 otherwise;
  *   max_workgroups  grid cap of the grid-stride launch (0 = one workgroup
- *                   per 256 * keys_per_lane keys);
+ *                   per workgroup_threads * keys_per_lane keys);
  *   strategy        add only: BF_STRATEGY_*.  The partitioned strategy
  *                   radix-partitions the keys by 64 KiB filter chunk and
  *                   updates each chunk in LDS, so a bulk add performs no
@@ -98,7 +98,13 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *                   for later adds); the library orders it against the
  *                   filter's other adds on any stream (see Concurrency).
  *                   Mapping fields other than strategy do not apply to it.
- *                   Results are identical. */
+ *                   Results are identical;
+ *   workgroup_threads threads per workgroup of the launch: 64, 128 or 256
+ *                   (sectorized layout; the other layouts run 256).
+ * The defaults come from a table measured on gfx950 per (operation, word
+ * bits, words per block, filter size class, k, batch size class: up to 2^16
+ * keys or more), so the mapping a call runs with may depend on n; bf_info
+ * reports the one for large batches. */
 typedef struct {
   uint32_t lanes_per_key;
   uint32_t words_per_lane;
@@ -106,6 +112,7 @@ typedef struct {
   uint32_t atomic_bits;
   uint32_t max_workgroups;
   uint32_t strategy;
+  uint32_t workgroup_threads;
 } bf_mapping_t;
 
 /* Filter layouts (bf_info_t.layout).  bf_create makes the sectorized
@@ -206,6 +213,15 @@ bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
  * partitioned add).  Host only: enqueues nothing and touches no device.
  * BF_EINVAL if f or out is NULL. */
 bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
+
+/* The mapping (and, for add, the construction strategy) that a sectorized
+ * filter of these parameters would run an operation of n keys with by
+ * default: the tuned row of (op, word_bits, words_per_block, size class of
+ * num_blocks * words_per_block * word_bits / 8 bytes, k, batch class of n)
+ * and, for add, the measured crossover of the layout.  Host only: touches no
+ * device.  BF_EINVAL for parameters bf_create rejects or a NULL out. */
+bf_status bf_tuned_mapping(int op, uint64_t num_blocks, uint32_t words_per_block,
+                           uint32_t word_bits, uint32_t k, uint64_t n, bf_mapping_t *out);
 
 /* For callers that cannot allocate device memory -- code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc: bf_add with

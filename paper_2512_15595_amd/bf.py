@@ -50,6 +50,7 @@ class bf_mapping_t(ctypes.Structure):
         ("atomic_bits", ctypes.c_uint32),
         ("max_workgroups", ctypes.c_uint32),
         ("strategy", ctypes.c_uint32),
+        ("workgroup_threads", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
@@ -94,6 +95,9 @@ _lib.bf_clear.argtypes = [_vp, _vp]
 _lib.bf_clear.restype = _i32
 _lib.bf_info.argtypes = [_vp, ctypes.POINTER(bf_info_t)]
 _lib.bf_info.restype = _i32
+_lib.bf_tuned_mapping.argtypes = [ctypes.c_int, _u64, _u32, _u32, _u32, _u64,
+                                  ctypes.POINTER(bf_mapping_t)]
+_lib.bf_tuned_mapping.restype = _i32
 _lib.bf_add_noalloc.argtypes = [_vp, _vp, _u64, _vp]
 _lib.bf_add_noalloc.restype = _i32
 _lib.bf_add_strategy.argtypes = [_vp, _u64, ctypes.POINTER(_u32)]
@@ -255,6 +259,15 @@ def bf_add(f, d_keys: int, n: int, stream: int = 0) -> int:
     return _lib.bf_add(f, d_keys, n, stream)
 
 
+def bf_tuned_mapping(op: int, num_blocks: int, words_per_block: int, word_bits: int, k: int,
+                     n: int):
+    """(status, bf_mapping_t): the default mapping and strategy of an
+    operation of n keys on such a filter (host only)."""
+    out = bf_mapping_t()
+    st = _lib.bf_tuned_mapping(op, num_blocks, words_per_block, word_bits, k, n, ctypes.byref(out))
+    return st, out
+
+
 def bf_add_noalloc(f, d_keys: int, n: int, stream: int = 0) -> int:
     return _lib.bf_add_noalloc(f, d_keys, n, stream)
 
@@ -288,9 +301,9 @@ def bf_set_mapping(f, op: int, lanes_per_key: int, words_per_lane: int, keys_per
 
 def bf_set_mapping_ex(f, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
                       keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0,
-                      strategy: int = 0) -> int:
+                      strategy: int = 0, workgroup_threads: int = 0) -> int:
     m = bf_mapping_t(lanes_per_key, words_per_lane, keys_per_lane, atomic_bits, max_workgroups,
-                     strategy)
+                     strategy, workgroup_threads)
     return _lib.bf_set_mapping_ex(f, op, ctypes.byref(m))
 
 
@@ -423,9 +436,10 @@ class _Filter:
 
     def set_mapping(self, op: int, lanes_per_key: int = 0, words_per_lane: int = 0,
                     keys_per_lane: int = 0, atomic_bits: int = 0, max_workgroups: int = 0,
-                    strategy: int = 0) -> None:
+                    strategy: int = 0, workgroup_threads: int = 0) -> None:
         _check(bf_set_mapping_ex(self._h, op, lanes_per_key, words_per_lane, keys_per_lane,
-                                 atomic_bits, max_workgroups, strategy), "bf_set_mapping_ex")
+                                 atomic_bits, max_workgroups, strategy, workgroup_threads),
+               "bf_set_mapping_ex")
 
     def words(self, stream=None):
         """A device copy of the words as a torch uint8 tensor."""

@@ -67,30 +67,39 @@ using namespace bfhip;
 
 namespace {
 
-bf_mapping_t default_mapping(const bf_filter* f, int op) {
+// The tuned default of one operation on f for a batch of n keys.
+bf_mapping_t default_mapping(const bf_filter* f, int op, uint64_t n) {
   const MapSpec t = tuned_map(op, static_cast<int>(f->word_bits), static_cast<int>(f->s),
-                              size_class_of(f->nbytes));
+                              size_class_of(f->nbytes), static_cast<int>(f->k), n_class_of(n));
   bf_mapping_t m{};
   m.lanes_per_key = t.theta;
   m.words_per_lane = t.phi;
   m.keys_per_lane = t.kt;
   m.atomic_bits = op == BF_OP_ADD ? t.atomic_bits : 0;
   m.max_workgroups = t.max_workgroups;
+  m.workgroup_threads = t.wg_threads;
   return m;
 }
 
-bf_mapping_t resolve_mapping(const bf_filter* f, int op) {
+// The mapping an operation of n keys runs with: the caller's fields, and
+// the tuned default for those left 0.
+bf_mapping_t resolve_mapping(const bf_filter* f, int op, uint64_t n) {
   if (f->layout != BF_LAYOUT_SECTORIZED) return variant_resolve_mapping(f, op);
   bf_mapping_t m = f->mapping[op];
+  const bf_mapping_t def = default_mapping(f, op, n);
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     const uint32_t cap = m.max_workgroups;
     const uint32_t ab = m.atomic_bits;
     const uint32_t strategy = m.strategy;
-    m = default_mapping(f, op);
-    m.max_workgroups = cap;
+    const uint32_t wg = m.workgroup_threads;
+    m = def;
+    if (cap != 0) m.max_workgroups = cap;
     m.strategy = strategy;
+    if (wg != 0) m.workgroup_threads = wg;
     if (ab != 0 && op == BF_OP_ADD && f->word_bits == 32 && m.words_per_lane >= 2) m.atomic_bits = ab;
   }
+  if (m.workgroup_threads == 0) m.workgroup_threads = def.workgroup_threads;
+  if (m.workgroup_threads == 0) m.workgroup_threads = kBlockThreads;
   if (m.atomic_bits == 0) m.atomic_bits = 32;
   if (k_index(f->k) == 0) {
     m.lanes_per_key = 1;
@@ -106,6 +115,9 @@ bf_status validate_mapping(const bf_filter* f, int op, const bf_mapping_t& m) {
   if (f->layout != BF_LAYOUT_SECTORIZED) return variant_validate_mapping(f, op, m);
   if (m.strategy > BF_STRATEGY_PARTITIONED) return BF_EINVAL;
   if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
+  if (!(m.workgroup_threads == 0 || m.workgroup_threads == 64 || m.workgroup_threads == 128 ||
+        m.workgroup_threads == 256))
+    return BF_EINVAL;
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) {
     // default mapping; only the atomic width may be forced
     if (m.atomic_bits != 0 && m.atomic_bits != 32 && m.atomic_bits != 64) return BF_EINVAL;
@@ -129,7 +141,7 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
   if (f->layout != BF_LAYOUT_SECTORIZED)
     return variant_launch(f, op, keys, n, out, static_cast<hipStream_t>(stream));
   ensure_registry();
-  bf_mapping_t m = resolve_mapping(f, op);
+  bf_mapping_t m = resolve_mapping(f, op, n);
   if (op == BF_OP_ADD && add_partitions(f, n))
     return partitioned_add(f, keys, n, static_cast<hipStream_t>(stream));
   // Keys per lane needs 8*KT-byte aligned keys (and KT-byte aligned results);
@@ -154,7 +166,8 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
                                                 static_cast<int>(kt), atom64)];
   if (fn == nullptr) return BF_EUNSUPPORTED;
 
-  const uint64_t tile = static_cast<uint64_t>(kBlockThreads) * kt;
+  const uint32_t wg = m.workgroup_threads;
+  const uint64_t tile = static_cast<uint64_t>(wg) * kt;
   const uint64_t ntiles = (n + tile - 1) / tile;
   uint64_t grid = ntiles;
   const uint64_t hard_cap = 1ull << 22;  // keeps grid * 256 below 2^32
@@ -171,8 +184,8 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
   a.nb_hi_mask = (f->num_blocks >> 32) ? 0xffffffffu : 0u;
   a.k = f->k;
   void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<uint32_t>(grid)), dim3(kBlockThreads), args,
-                                 0, static_cast<hipStream_t>(stream));
+  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<uint32_t>(grid)), dim3(wg), args, 0,
+                                 static_cast<hipStream_t>(stream));
   if (e != hipSuccess) return BF_EDEVICE;
   return BF_OK;
 }
@@ -287,18 +300,49 @@ bf_status bfhip::alloc_filter_words(bf_filter* f) {
   return BF_OK;
 }
 
+// The measured cost model of the two constructions for f's layout (the
+// autotuner's crossover rows; nullptr if the layout has none).
+const CrossoverRow* bfhip::crossover_of(const bf_filter* f) {
+  switch (f->layout) {
+    case BF_LAYOUT_SECTORIZED:
+      return crossover_row(0, static_cast<int>(f->word_bits), static_cast<int>(f->s), 0, 0);
+    case BF_LAYOUT_CLASSIC:
+      return crossover_row(1, 32, 1, 0, static_cast<int>(f->k));
+    case BF_LAYOUT_CACHE_SECTORIZED:
+      return crossover_row(2, static_cast<int>(f->word_bits), static_cast<int>(f->s),
+                           static_cast<int>(f->groups), 0);
+    default:
+      return nullptr;
+  }
+}
+
+// Whether n keys are dense enough in a filter of `bytes` for a partitioned
+// construction, by the layout's measured costs: partitioned ~ a + b * MiB +
+// c * n against direct ~ d * n (d of the filter's size class).  With
+// marginal_only the fixed cost a is left out (a batched plan shares it over
+// its filters).  Without a measured row: 1.5 M keys + bytes / 80 (the
+// sectorized 256-bit layout's fit).
+bool bfhip::dense_enough(const CrossoverRow* r, uint64_t bytes, uint64_t n, bool marginal_only) {
+  if (r == nullptr) return n >= (marginal_only ? 0 : 3 * (1ull << 19)) + bytes / 80;
+  const double gain = r->d_ps[size_class_of(bytes)] - r->c_ps;  // ps saved per key
+  if (gain <= 0.0) return false;
+  const double cost_us = (marginal_only ? 0.0 : r->a_us) +
+                         r->b_us_per_mib * static_cast<double>(bytes) / (1 << 20);
+  return static_cast<double>(n) * gain * 1e-6 > cost_us;
+}
+
 // Strategy of one bulk add: partitioned when asked for, or (auto) when the
 // batch is dense enough for streaming the touched chunks to beat one
-// memory-side atomic group per key.  Measured on MI355X (8 x 32-bit blocks,
-// 2^16..2^26 keys, 4 MiB..1 GiB): a partitioned add costs ~34 us + 0.45 ms
-// per GB of filter (each touched chunk read and written once) + 10 ms per
-// 10^9 keys, a direct add 40 (caches) to 51 (HBM) ms per 10^9 keys; the
-// crossover is about 1.5 M keys + filter bytes / 80.
+// memory-side atomic group per key (n counts records: k per key for the
+// classic layout).
 bool bfhip::use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m) {
   if (m.strategy == BF_STRATEGY_DIRECT) return false;
   if (!partition_applicable(f, n)) return false;
   if (m.strategy == BF_STRATEGY_PARTITIONED) return true;
-  return n >= 3 * (1ull << 19) + f->nbytes / 80;
+  const CrossoverRow* r = crossover_of(f);
+  // the classic rows are measured in keys, the fallback rule in records
+  const uint64_t units = (r != nullptr && f->layout == BF_LAYOUT_CLASSIC) ? n / f->k : n;
+  return dense_enough(r, f->nbytes, units, false);
 }
 
 bool bfhip::add_partitions(const bf_filter* f, uint64_t n) {
@@ -446,8 +490,8 @@ bf_status bf_info(const bf_filter* f, bf_info_t* out) {
   i.seed = f->seed;
   i.size_bytes = f->nbytes;
   i.d_words = f->d_words;
-  i.mapping[BF_OP_ADD] = resolve_mapping(f, BF_OP_ADD);
-  i.mapping[BF_OP_CONTAINS] = resolve_mapping(f, BF_OP_CONTAINS);
+  i.mapping[BF_OP_ADD] = resolve_mapping(f, BF_OP_ADD, ~0ull);
+  i.mapping[BF_OP_CONTAINS] = resolve_mapping(f, BF_OP_CONTAINS, ~0ull);
   i.layout = f->layout;
   i.groups = f->groups;
   i.num_bits = f->num_bits;
@@ -458,6 +502,30 @@ bf_status bf_info(const bf_filter* f, bf_info_t* out) {
 bf_status bf_add_strategy(const bf_filter* f, uint64_t n, uint32_t* out) {
   if (f == nullptr || out == nullptr) return BF_EINVAL;
   *out = add_partitions(f, n) ? BF_STRATEGY_PARTITIONED : BF_STRATEGY_DIRECT;
+  return BF_OK;
+}
+
+bf_status bf_tuned_mapping(int op, uint64_t num_blocks, uint32_t words_per_block,
+                           uint32_t word_bits, uint32_t k, uint64_t n, bf_mapping_t* out) {
+  const uint32_t s = words_per_block;
+  if (out == nullptr || (op != BF_OP_ADD && op != BF_OP_CONTAINS)) return BF_EINVAL;
+  if (!(s == 1 || s == 2 || s == 4 || s == 8 || s == 16)) return BF_EINVAL;
+  if (!(word_bits == 32 || word_bits == 64)) return BF_EINVAL;
+  if (k < s || k > static_cast<uint32_t>(kMaxK)) return BF_EINVAL;
+  if (num_blocks < 1 || num_blocks > (1ull << 32)) return BF_EINVAL;
+  bf_filter f{};  // host-side description only: no words
+  f.layout = BF_LAYOUT_SECTORIZED;
+  f.num_blocks = num_blocks;
+  f.s = s;
+  f.word_bits = word_bits;
+  f.k = k;
+  f.nbytes = num_blocks * s * (word_bits / 8);
+  f.num_bits = f.nbytes * 8;
+  bf_mapping_t m = resolve_mapping(&f, op, n);
+  m.strategy = op == BF_OP_ADD ? (add_partitions(&f, n) ? BF_STRATEGY_PARTITIONED
+                                                          : BF_STRATEGY_DIRECT)
+                               : BF_STRATEGY_AUTO;
+  *out = m;
   return BF_OK;
 }
 

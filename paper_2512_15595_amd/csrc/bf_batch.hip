@@ -54,9 +54,12 @@ struct bf_batch {
 
 namespace {
 
+// The mapping the batched kernel compiles in for a size class (bf_batch_kernels.hpp:
+// batch_map): the tuned rows of large batches at the filters' k.
 MapSpec class_map(int op, const bf_filter* f, int cls) {
-  if (k_index(f->k) == 0) return MapSpec{1, f->s, 1, 32, 0, true};
-  return tuned_map(op, static_cast<int>(f->word_bits), static_cast<int>(f->s), cls);
+  if (k_index(f->k) == 0) return MapSpec{1, f->s, 1, 32, 0, kBlockThreads, true};
+  return tuned_map(op, static_cast<int>(f->word_bits), static_cast<int>(f->s), cls,
+                   static_cast<int>(f->k), 1);
 }
 
 void free_plan(bf_batch* b) {
@@ -71,11 +74,12 @@ void free_plan(bf_batch* b) {
 // Partitioned construction for an add plan: the filters' blocks are laid
 // end to end in one global block space (each filter starting on a chunk
 // boundary), so one radix partition groups every key of every filter by
-// global chunk.  With the automatic strategy a filter with fewer keys than
-// its bytes / 80 is left to the direct launch (b->part_direct): streaming
-// its chunks would cost more than its keys' atomics (the single-filter
-// crossover of the same construction), and its chunks then get neither
-// records nor traffic.  Returns BF_OK and sets b->partitioned when taken.
+// global chunk.  With the automatic strategy a filter whose keys are too
+// few for its size is left to the direct launch (b->part_direct): by the
+// layout's measured costs (the crossover rows of bf_tuned.hpp, without the
+// fixed cost, which the plan shares), streaming its chunks would cost more
+// than its keys' atomics, and its chunks then get neither records nor
+// traffic.  Returns BF_OK and sets b->partitioned when taken.
 bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfilters,
                            const uint64_t* d_keys, const uint64_t* h_offsets) {
   const bf_filter* f0 = filters[0];
@@ -86,6 +90,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   const uint32_t shift = part_chunk_shift(f0->s, f0->word_bits);
   const uint64_t bpc = 1ull << shift;
   std::vector<PartFilter> pf(nfilters);
+  const CrossoverRow* xr = crossover_of(f0);
   uint64_t chunks = 0;
   for (uint32_t i = 0; i < nfilters; ++i) {
     const bf_filter* f = filters[i];
@@ -100,7 +105,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
     pf[i].key_end = h_offsets[i + 1] - h_offsets[0];
     const uint64_t ni = pf[i].key_end - pf[i].key_begin;
     const uint64_t nc = (f->num_blocks + bpc - 1) / bpc;
-    pf[i].direct = !forced && ni * 80 < f->nbytes ? 1u : 0u;
+    pf[i].direct = !forced && !dense_enough(xr, f->nbytes, ni, true) ? 1u : 0u;
     if (!pf[i].direct) {
       n_dense += ni;
       dense_chunks += nc;
@@ -288,6 +293,7 @@ bf_status build_tiles(bf_batch* b, bf_filter* const* filters, uint32_t nfilters,
     bm.words_per_lane = m.phi;
     bm.keys_per_lane = m.kt;
     bm.atomic_bits = op == BF_OP_ADD ? m.atomic_bits : 0;
+    bm.workgroup_threads = kBlockThreads;  // tiles are planned at this size
     b->mapping[c] = bm;
   }
 

@@ -42,14 +42,16 @@ struct BatchArgs {
   uint32_t pad;
 };
 
-// The mapping a size class runs with.  Runtime-k layouts use one lane per
-// key and one key per lane, as the single-filter path does.
+// The mapping a size class runs with (256-thread workgroups: tiles are
+// planned on the host at that size).  Runtime-k layouts use one lane per key
+// and one key per lane, as the single-filter path does.
 template <typename W, int S_WORDS, int K, int OP, int CLS>
 constexpr MapSpec batch_map() {
   if constexpr (K == 0) {
-    return MapSpec{1, static_cast<uint32_t>(S_WORDS), 1, 32, 0, true};
+    return MapSpec{1, static_cast<uint32_t>(S_WORDS), 1, 32, 0, kBlockThreads, true};
   } else {
-    return tuned_map(OP, 8 * static_cast<int>(sizeof(W)), S_WORDS, CLS);
+    // batched launches are large: the tuned rows of large batches at k
+    return tuned_map(OP, 8 * static_cast<int>(sizeof(W)), S_WORDS, CLS, K, 1);
   }
 }
 

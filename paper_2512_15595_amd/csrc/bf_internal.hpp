@@ -93,6 +93,12 @@ bf_status alloc_filter_words(bf_filter* f);
 bf_status launch_unordered(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,
                            hipStream_t stream);
 
+// The measured construction costs of f's layout (bf_tuned.hpp rows; nullptr
+// if none) and the density rule built on them (bf_api.hip).
+struct CrossoverRow;
+const CrossoverRow* crossover_of(const bf_filter* f);
+bool dense_enough(const CrossoverRow* r, uint64_t bytes, uint64_t n, bool marginal_only);
+
 // Whether a bulk add of n keys takes the partitioned strategy (bf_api.hip).
 bool use_partitioned(const bf_filter* f, uint64_t n, const bf_mapping_t& m);
 // Whether bf_add of n keys on f takes the partitioned construction (the

@@ -330,19 +330,20 @@ __device__ __forceinline__ void contains_tile(const FilterView& fv, const uint64
 }
 
 // ---------------------------------------------------------------------------
-// Single-filter kernels: a grid-stride walk over the tiles of one key array.
-// The host guarantees 8*KT-byte aligned keys and KT-byte aligned results.
+// Single-filter kernels: a grid-stride walk over the tiles of one key array,
+// a tile being blockDim.x * KT keys (the workgroup size is a tuned knob: 64,
+// 128 or 256 threads, whole wavefronts).  The host guarantees 8*KT-byte
+// aligned keys and KT-byte aligned results.
 // ---------------------------------------------------------------------------
 template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
 __global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
   const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
   const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
-  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
-  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint64_t base = tile * kTile;
-    const uint32_t count = static_cast<uint32_t>(a.n - base < kTile ? a.n - base : kTile);
-    add_tile<W, S_WORDS, K, THETA, PHI, KT, ATOM64>(fv, a.keys + base, count, count == kTile,
+  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * KT;
+  const uint64_t stride = tile * gridDim.x;
+  for (uint64_t base = blockIdx.x * tile; base < a.n; base += stride) {
+    const uint32_t count = static_cast<uint32_t>(a.n - base < tile ? a.n - base : tile);
+    add_tile<W, S_WORDS, K, THETA, PHI, KT, ATOM64>(fv, a.keys + base, count, count == tile,
                                                     a.k, lp);
   }
 }
@@ -351,13 +352,12 @@ template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT>
 __global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
   const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
   const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
-  constexpr uint64_t kTile = static_cast<uint64_t>(kBlockThreads) * KT;
-  const uint64_t ntiles = (a.n + kTile - 1) / kTile;
-  for (uint64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const uint64_t base = tile * kTile;
-    const uint32_t count = static_cast<uint32_t>(a.n - base < kTile ? a.n - base : kTile);
+  const uint64_t tile = static_cast<uint64_t>(blockDim.x) * KT;
+  const uint64_t stride = tile * gridDim.x;
+  for (uint64_t base = blockIdx.x * tile; base < a.n; base += stride) {
+    const uint32_t count = static_cast<uint32_t>(a.n - base < tile ? a.n - base : tile);
     contains_tile<W, S_WORDS, K, THETA, PHI, KT>(fv, a.keys + base, a.out + base, count,
-                                                 count == kTile, a.k, lp);
+                                                 count == tile, a.k, lp);
   }
 }
 

@@ -120,10 +120,12 @@ bool coalescable(const bf_server* s, const Pending& p) {
          s->cfg.coalesce_max_requests > 1;
 }
 
+// The mapping a coalesced launch runs a request's tiles with: the batched
+// kernel's (large-batch rows at the filter's k, 256-thread tiles).
 MapSpec request_map(const bf_filter* f, int op) {
-  if (k_index(f->k) == 0) return MapSpec{1, f->s, 1, 32, 0, true};
+  if (k_index(f->k) == 0) return MapSpec{1, f->s, 1, 32, 0, kBlockThreads, true};
   return tuned_map(op, static_cast<int>(f->word_bits), static_cast<int>(f->s),
-                   size_class_of(f->nbytes));
+                   size_class_of(f->nbytes), static_cast<int>(f->k), 1);
 }
 
 uint64_t tiles_of(const bf_filter* f, const Pending& p) {

@@ -164,6 +164,7 @@ bf_mapping_t variant_resolve_mapping(const bf_filter* f, int op) {
   }
   if (m.keys_per_lane == 0) m.keys_per_lane = 1;
   m.atomic_bits = op == BF_OP_ADD ? 32 : 0;
+  m.workgroup_threads = kBlockThreads;
   // lookups have no strategy; adds that cannot be partitioned are direct
   if (op == BF_OP_CONTAINS)
     m.strategy = BF_STRATEGY_AUTO;
@@ -178,6 +179,7 @@ bf_status variant_validate_mapping(const bf_filter* f, int op, const bf_mapping_
     return BF_EUNSUPPORTED;
   if (op == BF_OP_CONTAINS && m.strategy != BF_STRATEGY_AUTO) return BF_EINVAL;
   if (!(m.atomic_bits == 0 || (op == BF_OP_ADD && m.atomic_bits == 32))) return BF_EINVAL;
+  if (!(m.workgroup_threads == 0 || m.workgroup_threads == kBlockThreads)) return BF_EINVAL;
   if (m.lanes_per_key == 0 && m.words_per_lane == 0 && m.keys_per_lane == 0) return BF_OK;
   if (f->layout == BF_LAYOUT_SECTORIZED_CHAINED) {
     if (m.lanes_per_key != 1 || (m.words_per_lane != 0 && m.words_per_lane != f->s) ||

@@ -246,15 +246,19 @@ def test_auto_strategy_matches_direct():
 
 def test_add_strategy_reports_the_construction():
     """bf_add_strategy resolves the automatic choice as bf_add does: direct
-    below about 1.5 M keys + filter bytes / 80, partitioned above; a forced
-    strategy wins; the classic layout counts k records per key; the chained
-    layout is never partitioned."""
+    for sparse batches, partitioned for dense ones, at the layout's measured
+    crossover (the same rule the host-only bf_tuned_mapping reports); a
+    forced strategy wins; the classic layout is measured in keys of k
+    records; the chained layout is never partitioned."""
     bf = _bf()
     f = bf.BloomFilter(1 << 20, 8, 32, 8, 3)                 # 32 MiB
     try:
         assert f.add_strategy(0) == bf.BF_STRATEGY_DIRECT
         assert f.add_strategy(1 << 20) == bf.BF_STRATEGY_DIRECT
         assert f.add_strategy(1 << 22) == bf.BF_STRATEGY_PARTITIONED
+        for n in (1 << 18, 1 << 20, 3 << 19, 1 << 21, 3 << 20, 1 << 22, 1 << 24):
+            st, m = bf.bf_tuned_mapping(bf.BF_OP_ADD, 1 << 20, 8, 32, 8, n)
+            assert st == 0 and f.add_strategy(n) == m.strategy
         f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_DIRECT)
         assert f.add_strategy(1 << 22) == bf.BF_STRATEGY_DIRECT
         f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
@@ -263,8 +267,8 @@ def test_add_strategy_reports_the_construction():
         f.close()
     c = bf.ClassicFilter(1 << 28, 8, 1)                      # 32 MiB, 8 records per key
     try:
-        assert c.add_strategy(1 << 17) == bf.BF_STRATEGY_DIRECT
-        assert c.add_strategy(1 << 18) == bf.BF_STRATEGY_PARTITIONED
+        assert c.add_strategy(1 << 15) == bf.BF_STRATEGY_DIRECT
+        assert c.add_strategy(1 << 20) == bf.BF_STRATEGY_PARTITIONED
     finally:
         c.close()
     h = bf.ChainedHashFilter(1 << 20, 8, 32, 8, 3)

@@ -168,8 +168,8 @@ def test_oversized_request_is_refused():
 
 def _dense_scenario(nfilters=8, nreq=48, seed=31):
     """Served mix whose adds take the partitioned construction: 4-16 MiB
-    filters, adds of 2-4 M keys (above the automatic crossover of about
-    1.5 M keys + bytes / 80), lookups of 10^3 - 2 * 10^6 keys, one add per
+    filters, adds of 2-4 M keys (above the measured automatic crossover,
+    about 1.7 M keys at 16 MiB), lookups of 10^3 - 2 * 10^6 keys, one add per
     three requests, all arriving within a few hundred microseconds."""
     g = workloads.rng(seed)
     block = 32
