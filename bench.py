@@ -445,6 +445,20 @@ def run_serve(args) -> dict:
     cap_res = srv.replay(reqs0, serial=True)
     cap = latency_summary(cap_res, ns[:ncap])["throughput_gkeys_s"] * 1e9
     log(f"[bench] serve: serial capacity {cap / 1e9:.2f} Gkeys/s")
+    # the device's capacity for this mix: the same requests all present at
+    # time 0, served with overlap; then lookups alone and adds alone (their
+    # rates at these request sizes bound any mix: 1 / (share / rate summed))
+    sat = latency_summary(srv.replay(reqs0), ns[:ncap])["throughput_gkeys_s"]
+    per_op = {}
+    for opv, name in ((1, "contains"), (0, "add")):
+        idx = np.flatnonzero(ops[:ncap] == opv)
+        r = srv.requests(ops[idx], filt[idx], [kp[i] for i in idx], ns[idx], [op_[i] for i in idx],
+                         np.zeros(idx.size))
+        per_op[name] = latency_summary(srv.replay(r), ns[idx])["throughput_gkeys_s"]
+    key_share_add = float(ns[:ncap][ops[:ncap] == 0].sum() / ns[:ncap].sum())
+    ceiling = 1.0 / (key_share_add / per_op["add"] + (1.0 - key_share_add) / per_op["contains"])
+    log(f"[bench] serve: saturated {sat:.2f} Gkeys/s; contains alone {per_op['contains']:.2f}, "
+        f"adds alone {per_op['add']:.2f}; mix ceiling {ceiling:.2f}")
     runs = {}
     mean_n = float(ns.mean())
     for load in args.serve_loads:
@@ -473,6 +487,9 @@ def run_serve(args) -> dict:
                    "max_inflight": args.serve_inflight, "streams": args.serve_streams,
                    "coalesce_max_keys": args.serve_coalesce_keys},
         "serial_capacity_gkeys_s": round(cap / 1e9, 3),
+        "saturated": {"served_gkeys_s": sat, "contains_only_gkeys_s": per_op["contains"],
+                      "adds_only_gkeys_s": per_op["add"], "add_key_share": round(key_share_add, 4),
+                      "mix_ceiling_gkeys_s": round(ceiling, 3)},
         "loads": runs,
         "server_stats": st,
     }
@@ -1187,7 +1204,7 @@ def main() -> int:
 def serve_summary(res: dict) -> dict:
     """The served leg's figures for the benchmark line."""
     out = {"workload": res["config"]["workload"], "requests": res["config"]["requests"],
-           "serial_capacity_gkeys_s": res["serial_capacity_gkeys_s"]}
+           "serial_capacity_gkeys_s": res["serial_capacity_gkeys_s"], "saturated": res["saturated"]}
     for load, r in res["loads"].items():
         out[f"load_{load}x"] = {
             "served_gkeys_s": r["served"]["throughput_gkeys_s"],

@@ -118,7 +118,8 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   PartArgs a{};
   PartLayout L{};
   if (!part_geometry(chunks, shift, n, a, L)) return BF_OK;
-  const PartKernels k = part_kernels(f0);
+  PartKernels k = part_kernels(f0);
+  if (nfilters > 1) k.scatter1 = k.scatter1_multi;  // the first pass walks a table of filters
   if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_OK;
   // Per-bucket capacities from each chunk's expected load: filter i's keys
   // spread uniformly over its blocks (a chunk holding part of the filter

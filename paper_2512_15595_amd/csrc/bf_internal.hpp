@@ -56,6 +56,7 @@ struct PartLayout {
 };
 struct PartKernels {
   const void* scatter1;
+  const void* scatter1_multi;  // first scatter of multi-filter plans (sectorized layout)
   const void* scatter2;
   const void* apply;
   uint32_t threads1;  // workgroup size of scatter1

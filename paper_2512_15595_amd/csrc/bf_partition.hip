@@ -126,7 +126,7 @@ PartKernels part_kernels(const bf_filter* f) {
     ensure_variant_registry();
     const VariantRegistry& r = variant_registry();
     const bool pow2 = (f->num_bits & (f->num_bits - 1)) == 0;
-    return PartKernels{r.classic_part1[k_index(f->k) * 2 + (pow2 ? 1 : 0)], r.classic_part2,
+    return PartKernels{r.classic_part1[k_index(f->k) * 2 + (pow2 ? 1 : 0)], nullptr, r.classic_part2,
                        r.classic_apply, kClassicThreads};
   }
   if (f->layout == BF_LAYOUT_CACHE_SECTORIZED) {
@@ -134,13 +134,14 @@ PartKernels part_kernels(const bf_filter* f) {
     const VariantRegistry& r = variant_registry();
     const int idx = csbf_part_index(static_cast<int>(f->word_bits), static_cast<int>(f->s),
                                     static_cast<int>(f->groups), k_index(f->k));
-    return PartKernels{r.csbf_part1[idx], r.csbf_part2[idx], r.csbf_apply[idx], kScatter1Threads};
+    return PartKernels{r.csbf_part1[idx], nullptr, r.csbf_part2[idx], r.csbf_apply[idx],
+                       kScatter1Threads};
   }
   ensure_registry();
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
-  return PartKernels{registry().part1_fn[idx], registry().part2_fn[idx], registry().apply_fn[idx],
-                     kScatter1Threads};
+  return PartKernels{registry().part1_fn[idx], registry().part1_multi_fn[idx], registry().part2_fn[idx],
+                     registry().apply_fn[idx], kScatter1Threads};
 }
 
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k,

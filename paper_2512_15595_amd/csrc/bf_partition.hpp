@@ -549,7 +549,10 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
   dst.publish();
 }
 
-template <typename W, int S_WORDS, int K, int Z = 0>
+// MULTI: the kernel of multi-filter plans.  The two loops are separate
+// kernels so that each gets its own register allocation (together they
+// needed more than the 128 VGPRs a 1024-thread workgroup allows, and spilled).
+template <typename W, int S_WORDS, int K, int Z = 0, bool MULTI = false>
 __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits> l;
   for (uint32_t d = threadIdx.x; d < a.f1; d += kScatter1Threads) {
@@ -557,10 +560,7 @@ __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArg
     l.fill[d] = 0;
   }
   __syncthreads();
-  if (a.nfilters > 1)
-    scatter1_loop<W, S_WORDS, K, Z, true>(a, l);
-  else
-    scatter1_loop<W, S_WORDS, K, Z, false>(a, l);
+  scatter1_loop<W, S_WORDS, K, Z, MULTI>(a, l);
 }
 
 // First pass of the classic filter: each key gives K records, one per
