@@ -176,12 +176,35 @@ def _simplicity(r):
             -r["atomic_bits"], -r["workgroup_threads"], r["max_workgroups"])
 
 
+def _mapping_of(r):
+    return (r["lanes_per_key"], r["words_per_lane"], r["keys_per_lane"], r["atomic_bits"],
+            r.get("workgroup_threads", 256), r["max_workgroups"])
+
+
+def _class_scores(rs):
+    """Per mapping measured at every filter size of the group: the mean over
+    those sizes of its rate relative to the best rate at that size (a size
+    class spans sizes whose best mappings can differ)."""
+    by_size = {}
+    for r in rs:
+        by_size.setdefault(r.get("filter_bytes", 0), {})[_mapping_of(r)] = r
+    common = set.intersection(*(set(v) for v in by_size.values()))
+    tops = {sz: max(r["gkeys_s"] for r in v.values()) for sz, v in by_size.items()}
+    rep = max(by_size, key=lambda sz: len(by_size[sz]))  # a record to report, per mapping
+    out = []
+    for m in common:
+        score = sum(by_size[sz][m]["gkeys_s"] / tops[sz] for sz in by_size) / len(by_size)
+        out.append((score, by_size[rep][m]))
+    return out
+
+
 def best_per_key(records, tolerance: float = 0.01, small_tolerance: float = 0.10):
-    """Fastest mapping per (op, word bits, words per block, size class, k,
-    batch class); mappings within `tolerance` of the fastest count as ties
-    and the simplest of them is taken, so run-to-run noise does not pick
-    exotic layouts.  Small batches are launch-latency bound and their rates
-    noisier (a launch of 2^15 keys takes ~7 us of device time, most of it
+    """Best mapping per (op, word bits, words per block, size class, k, batch
+    class): the highest mean relative rate over the filter sizes measured in
+    the class; mappings within `tolerance` of the best count as ties and the
+    simplest of them is taken, so run-to-run noise does not pick exotic
+    layouts.  Small batches are launch-latency bound and their rates noisier
+    (a launch of 2^15 keys takes ~7 us of device time, most of it
     dispatch): their band is `small_tolerance`, and the large-batch mapping
     is kept when it is inside it."""
     groups = {}
@@ -193,20 +216,20 @@ def best_per_key(records, tolerance: float = 0.01, small_tolerance: float = 0.10
     for key, rs in groups.items():
         if key[5] == 0:
             continue
-        top = max(r["gkeys_s"] for r in rs)
-        ties = [r for r in rs if r["gkeys_s"] >= (1.0 - tolerance) * top]
+        scored = _class_scores(rs)
+        top = max(sc for sc, _ in scored)
+        ties = [r for sc, r in scored if sc >= (1.0 - tolerance) * top]
         best[key] = min(ties, key=_simplicity)
     # a small batch keeps the large-batch mapping unless another one is
     # clearly faster at its size
     for key, rs in groups.items():
         if key[5] != 0:
             continue
-        top = max(r["gkeys_s"] for r in rs)
-        ties = [r for r in rs if r["gkeys_s"] >= (1.0 - small_tolerance) * top]
+        scored = _class_scores(rs)
+        top = max(sc for sc, _ in scored)
+        ties = [r for sc, r in scored if sc >= (1.0 - small_tolerance) * top]
         large = best.get(key[:5] + (1,))
-        same = [r for r in ties if large is not None and all(
-            r[f] == large[f] for f in ("lanes_per_key", "words_per_lane", "keys_per_lane",
-                                       "atomic_bits", "workgroup_threads"))]
+        same = [r for r in ties if large is not None and _mapping_of(r) == _mapping_of(large)]
         best[key] = same[0] if same else min(ties, key=_simplicity)
     return best
 
@@ -338,8 +361,8 @@ def emit_inc(records, xover_records=None, path: str = INC_PATH) -> str:
 
 def main() -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--sizes-log2", type=int, nargs="+", default=[21, 26, 30],
-                    help="filter sizes (one per size class) for the mapping sweep")
+    ap.add_argument("--sizes-log2", type=int, nargs="+", default=[21, 24, 26, 30],
+                    help="filter sizes for the mapping sweep (a class may hold several)")
     ap.add_argument("--ks", type=int, nargs="+", default=list(TUNED_KS))
     ap.add_argument("--ns-log2", type=int, nargs="+", default=[15, 26],
                     help="batch sizes (one per batch class) for the mapping sweep")
