@@ -7,9 +7,9 @@ every lookup result comes from one call of the oracle's own C functions.
 The work is split so that the calls touch disjoint outputs:
 
 * the words of a filter are built block range by block range
-  (``oracle.block_words`` over a contiguous range of blocks, which applies
-  exactly the keys that select a block of the range), and the ranges are
-  concatenated;
+  (``oracle.block_words`` -- or ``csbf_block_words``, or ``classic_words``
+  over ranges of 64-bit words -- over a contiguous range, which applies
+  exactly the keys that reach the range), and the ranges are concatenated;
 * lookups are split into query slices, each answered by
   ``OracleFilter.contains`` semantics over the complete oracle words.
 
@@ -25,7 +25,8 @@ import os
 
 import numpy as np
 
-from . import OracleFilter, block_words
+from . import (ClassicOracle, CsbfOracle, OracleFilter, block_words, classic_words,
+               csbf_block_words)
 
 
 def workers(limit: int = 16) -> int:
@@ -43,38 +44,58 @@ def _ranges(total: int, parts: int):
     return [(lo, min(total, lo + step)) for lo in range(0, total, step)] or [(0, 0)]
 
 
+def _by_ranges(units: int, unit_bytes: int, rows_of, threads: int | None, parts: int | None):
+    """Filter bytes assembled from rows_of(sel) -- the oracle's bytes of the
+    units (blocks or words) sel -- over contiguous unit ranges."""
+    out = np.zeros(units * unit_bytes, dtype=np.uint8)
+    threads = threads or workers()
+
+    def one(r):
+        lo, hi = r
+        if hi > lo:
+            rows = rows_of(np.arange(lo, hi, dtype=np.uint64))
+            out[lo * unit_bytes:hi * unit_bytes] = np.ascontiguousarray(rows).view(np.uint8).reshape(-1)
+
+    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
+        list(ex.map(one, _ranges(units, parts or threads)))
+    return out
+
+
 def filter_words(num_blocks: int, words_per_block: int, word_bits: int, k: int, seed: int,
                  keys: np.ndarray, threads: int | None = None, parts: int | None = None) -> np.ndarray:
     """The oracle's filter bytes after adding `keys`, built by block ranges."""
     keys = np.ascontiguousarray(keys, dtype=np.uint64)
-    block_bytes = words_per_block * word_bits // 8
-    out = np.zeros(num_blocks * block_bytes, dtype=np.uint8)
-    threads = threads or workers()
-    ranges = _ranges(num_blocks, parts or threads)
-
-    def one(r):
-        lo, hi = r
-        if hi <= lo:
-            return
-        sel = np.arange(lo, hi, dtype=np.uint64)
-        rows = block_words(num_blocks, words_per_block, word_bits, k, seed, keys, sel)
-        out[lo * block_bytes:hi * block_bytes] = rows.reshape(-1)
-
-    with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
-        list(ex.map(one, ranges))
-    return out
+    return _by_ranges(num_blocks, words_per_block * word_bits // 8,
+                      lambda sel: block_words(num_blocks, words_per_block, word_bits, k, seed, keys, sel),
+                      threads, parts)
 
 
-def contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, word_bits: int,
-             k: int, seed: int, queries: np.ndarray, threads: int | None = None) -> np.ndarray:
-    """The oracle's lookup result of every query against `filter_bytes`
-    (oracle words), by query slices."""
+def csbf_filter_words(num_blocks: int, words_per_block: int, word_bits: int, groups: int, k: int,
+                      seed: int, keys: np.ndarray, threads: int | None = None,
+                      parts: int | None = None) -> np.ndarray:
+    """The cache-sectorized oracle's filter bytes after adding `keys`, by block ranges."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    return _by_ranges(num_blocks, words_per_block * word_bits // 8,
+                      lambda sel: csbf_block_words(num_blocks, words_per_block, word_bits, groups, k,
+                                                   seed, keys, sel),
+                      threads, parts)
+
+
+def classic_filter_words(num_bits: int, k: int, seed: int, keys: np.ndarray,
+                         threads: int | None = None, parts: int | None = None) -> np.ndarray:
+    """The classic oracle's filter bytes after adding `keys`, by ranges of
+    64-bit words."""
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    return _by_ranges(num_bits // 64, 8, lambda sel: classic_words(num_bits, k, seed, keys, sel),
+                      threads, parts)
+
+
+def lookups(view, queries: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """view.contains(q) of every query, by query slices; `view` is an oracle
+    filter object (any layout) holding the state to look up in."""
     queries = np.ascontiguousarray(queries, dtype=np.uint64)
     out = np.zeros(queries.size, dtype=np.uint8)
     threads = threads or workers()
-    view = OracleFilter(num_blocks, words_per_block, word_bits, k, seed)
-    assert filter_bytes.size == view.nbytes
-    view.bytes = filter_bytes  # the zero state it allocated is never touched
 
     def one(r):
         lo, hi = r
@@ -84,6 +105,35 @@ def contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, wo
     with concurrent.futures.ThreadPoolExecutor(max_workers=threads) as ex:
         list(ex.map(one, _ranges(queries.size, 4 * threads)))
     return out
+
+
+def _holding(view, filter_bytes: np.ndarray):
+    assert filter_bytes.size == view.nbytes
+    view.bytes = filter_bytes  # the zero state it allocated is never touched
+    return view
+
+
+def contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, word_bits: int,
+             k: int, seed: int, queries: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """The oracle's lookup result of every query against `filter_bytes`
+    (oracle words), by query slices."""
+    view = _holding(OracleFilter(num_blocks, words_per_block, word_bits, k, seed), filter_bytes)
+    return lookups(view, queries, threads)
+
+
+def csbf_contains(filter_bytes: np.ndarray, num_blocks: int, words_per_block: int, word_bits: int,
+                  groups: int, k: int, seed: int, queries: np.ndarray,
+                  threads: int | None = None) -> np.ndarray:
+    """Cache-sectorized oracle lookups against `filter_bytes`, by query slices."""
+    view = _holding(CsbfOracle(num_blocks, words_per_block, word_bits, groups, k, seed), filter_bytes)
+    return lookups(view, queries, threads)
+
+
+def classic_contains(filter_bytes: np.ndarray, num_bits: int, k: int, seed: int,
+                     queries: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """Classic oracle lookups against `filter_bytes`, by query slices."""
+    view = _holding(ClassicOracle(num_bits, k, seed), filter_bytes)
+    return lookups(view, queries, threads)
 
 
 def per_filter(jobs, fn, threads: int | None = None):
