@@ -98,6 +98,12 @@ def _load():
         lib.oracle_chained_add.restype = i32
         lib.oracle_chained_contains.argtypes = [vp, u64, u32, u32, u32, u64, vp, u64, vp]
         lib.oracle_chained_contains.restype = i32
+        lib.oracle_parquet_add.argtypes = [vp, u64, vp, u64]
+        lib.oracle_parquet_add.restype = i32
+        lib.oracle_parquet_contains.argtypes = [vp, u64, vp, u64, vp]
+        lib.oracle_parquet_contains.restype = i32
+        lib.oracle_parquet_block_words.argtypes = [u64, vp, u64, vp, u64, vp]
+        lib.oracle_parquet_block_words.restype = i32
         _lib = lib
     return _lib
 
@@ -337,3 +343,40 @@ class ChainedOracle(OracleFilter):
                                              keys.size, _ptr(out))
         assert rc == 0
         return out[: keys.size]
+
+
+class ParquetOracle:
+    """Parquet split-block filter of num_bytes bytes (the format's bitset)."""
+
+    def __init__(self, num_bytes: int):
+        if num_bytes < 32 or num_bytes % 32 or num_bytes // 32 > 2**32:
+            raise ValueError("num_bytes must be a multiple of 32 in [32, 2^37]")
+        self.nbytes = num_bytes
+        self.bytes = np.zeros(num_bytes, dtype=np.uint8)
+
+    def add(self, values) -> None:
+        values = _keys(values)
+        assert _load().oracle_parquet_add(_ptr(self.bytes), self.nbytes, _ptr(values), values.size) == 0
+
+    def contains(self, values) -> np.ndarray:
+        values = _keys(values)
+        out = np.zeros(max(values.size, 1), dtype=np.uint8)
+        assert _load().oracle_parquet_contains(_ptr(self.bytes), self.nbytes, _ptr(values),
+                                               values.size, _ptr(out)) == 0
+        return out[: values.size]
+
+    def clear(self) -> None:
+        _load().oracle_clear(_ptr(self.bytes), self.nbytes)
+
+
+def parquet_block_words(num_bytes: int, values, blocks) -> np.ndarray:
+    """Bytes of the selected blocks of a Parquet split-block filter after
+    adding ``values`` (one 32-byte row per block)."""
+    values = _keys(values)
+    sel = np.ascontiguousarray(np.asarray(blocks, dtype=np.uint64))
+    out = np.zeros((max(sel.size, 1), 32), dtype=np.uint8)
+    rc = _load().oracle_parquet_block_words(num_bytes, _ptr(values), values.size, _ptr(sel),
+                                            sel.size, _ptr(out))
+    if rc != 0:
+        raise ValueError("bad parameters or block selection")
+    return out[: sel.size]

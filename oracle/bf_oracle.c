@@ -535,3 +535,83 @@ int oracle_chained_contains(const uint8_t *filter, uint64_t num_blocks,
                                         words_per_block, word_bits, k, 0);
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Parquet split-block Bloom filter (the Apache Parquet format; the paper's  */
+/* Arrow / Parquet-compatible configuration, Sec. I and Sec. VI).            */
+/* ------------------------------------------------------------------------ */
+
+/* The format's eight odd multipliers, one per word of a block. */
+static const uint32_t PARQUET_SALT[8] = {
+    0x47b6137bu, 0x44974d91u, 0x8824ad5bu, 0xa2b7289du,
+    0x705495c7u, 0x2df1424bu, 0x9efc4947u, 0x5c6bfb31u,
+};
+
+static int parquet_ok(uint64_t num_bytes) {
+    return num_bytes >= 32 && num_bytes % 32 == 0 && num_bytes / 32 <= (1ULL << 32);
+}
+
+/* The block a value maps to and the bit it sets in each of the block's
+ * eight words. */
+static uint64_t parquet_locate(uint64_t value, uint64_t num_blocks, unsigned bit[8]) {
+    uint64_t h = oracle_hash_key(value, 0);       /* XXH64(8 LE bytes, seed 0) */
+    uint32_t lo = (uint32_t)(h & 0xFFFFFFFFULL);
+    for (int i = 0; i < 8; ++i) {
+        uint32_t product = lo * PARQUET_SALT[i];  /* mod 2^32 */
+        bit[i] = product >> 27;                   /* in [0, 32) */
+    }
+    return ((h >> 32) * num_blocks) >> 32;
+}
+
+int oracle_parquet_add(uint8_t *filter, uint64_t num_bytes, const uint64_t *values,
+                       uint64_t n) {
+    if (!parquet_ok(num_bytes)) return -1;
+    uint64_t num_blocks = num_bytes / 32;
+    unsigned bit[8];
+    for (uint64_t v = 0; v < n; ++v) {
+        uint64_t blk = parquet_locate(values[v], num_blocks, bit);
+        for (int i = 0; i < 8; ++i) set_bit(filter, blk * 8 + (uint64_t)i, 32, bit[i]);
+    }
+    return 0;
+}
+
+int oracle_parquet_contains(const uint8_t *filter, uint64_t num_bytes,
+                            const uint64_t *values, uint64_t n, uint8_t *out) {
+    if (!parquet_ok(num_bytes)) return -1;
+    uint64_t num_blocks = num_bytes / 32;
+    unsigned bit[8];
+    for (uint64_t v = 0; v < n; ++v) {
+        uint64_t blk = parquet_locate(values[v], num_blocks, bit);
+        int all_set = 1;
+        for (int i = 0; i < 8; ++i)
+            if (!get_bit(filter, blk * 8 + (uint64_t)i, 32, bit[i])) all_set = 0;
+        out[v] = (uint8_t)all_set;
+    }
+    return 0;
+}
+
+int oracle_parquet_block_words(uint64_t num_bytes, const uint64_t *values, uint64_t n,
+                               const uint64_t *sel, uint64_t nsel, uint8_t *out) {
+    if (!parquet_ok(num_bytes)) return -1;
+    uint64_t num_blocks = num_bytes / 32;
+    uint32_t *slot_of = (uint32_t *)calloc(num_blocks, sizeof(uint32_t));
+    if (!slot_of) return -1;
+    for (uint64_t i = 0; i < nsel; ++i) {
+        if (sel[i] >= num_blocks || slot_of[sel[i]] != 0 || nsel >= 0xFFFFFFFFULL) {
+            free(slot_of);
+            return -1;
+        }
+        slot_of[sel[i]] = (uint32_t)(i + 1);
+    }
+    memset(out, 0, nsel * 32);
+    unsigned bit[8];
+    for (uint64_t v = 0; v < n; ++v) {
+        uint64_t blk = parquet_locate(values[v], num_blocks, bit);
+        uint32_t slot = slot_of[blk];
+        if (slot == 0) continue;
+        uint8_t *dst = out + (uint64_t)(slot - 1) * 32;
+        for (int i = 0; i < 8; ++i) set_bit(dst, (uint64_t)i, 32, bit[i]);
+    }
+    free(slot_of);
+    return 0;
+}

@@ -148,6 +148,28 @@ int oracle_chained_contains(const uint8_t *filter, uint64_t num_blocks,
                             uint32_t words_per_block, uint32_t word_bits, uint32_t k,
                             uint64_t seed, const uint64_t *keys, uint64_t n, uint8_t *out);
 
+/* ------------------------------------------------------------------------
+ * Apache Parquet split-block Bloom filter, the Arrow / Parquet-compatible
+ * configuration the paper names (Sec. I and Sec. VI).  The format's
+ * definition: num_bytes / 32 blocks of eight little-endian 32-bit words; a
+ * value hashes to h = XXH64 of its plain encoding with seed 0 (for the
+ * 8-byte types INT64 and DOUBLE: its 8 little-endian bytes, i.e. the key);
+ * block = ((h >> 32) * num_blocks) >> 32; word i of that block (i = 0..7)
+ * gets bit ((lo32(h) * c_i) mod 2^32) >> 27, c_i the format's eight odd
+ * constants.  num_bytes: a multiple of 32, 32 <= num_bytes <= 2^37.  The
+ * state's bytes are the bitset a Parquet file stores after the filter's
+ * header.  Pinned against the bitsets Apache Arrow writes into Parquet
+ * files (tests).
+ * ------------------------------------------------------------------------ */
+int oracle_parquet_add(uint8_t *filter, uint64_t num_bytes, const uint64_t *values,
+                       uint64_t n);
+int oracle_parquet_contains(const uint8_t *filter, uint64_t num_bytes,
+                            const uint64_t *values, uint64_t n, uint8_t *out);
+/* The selected blocks' 32 bytes each after adding values (as
+ * oracle_block_words: sel distinct, in range). */
+int oracle_parquet_block_words(uint64_t num_bytes, const uint64_t *values, uint64_t n,
+                               const uint64_t *sel, uint64_t nsel, uint8_t *out);
+
 #ifdef __cplusplus
 }
 #endif

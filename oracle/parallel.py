@@ -25,8 +25,8 @@ import os
 
 import numpy as np
 
-from . import (ClassicOracle, CsbfOracle, OracleFilter, block_words, classic_words,
-               csbf_block_words)
+from . import (ClassicOracle, CsbfOracle, OracleFilter, ParquetOracle, block_words,
+               classic_words, csbf_block_words, parquet_block_words)
 
 
 def workers(limit: int = 16) -> int:
@@ -90,6 +90,14 @@ def classic_filter_words(num_bits: int, k: int, seed: int, keys: np.ndarray,
                       threads, parts)
 
 
+def parquet_filter_words(num_bytes: int, values: np.ndarray, threads: int | None = None,
+                         parts: int | None = None) -> np.ndarray:
+    """The Parquet split-block oracle's bitset after adding `values`, by block ranges."""
+    values = np.ascontiguousarray(values, dtype=np.uint64)
+    return _by_ranges(num_bytes // 32, 32, lambda sel: parquet_block_words(num_bytes, values, sel),
+                      threads, parts)
+
+
 def lookups(view, queries: np.ndarray, threads: int | None = None) -> np.ndarray:
     """view.contains(q) of every query, by query slices; `view` is an oracle
     filter object (any layout) holding the state to look up in."""
@@ -133,6 +141,13 @@ def classic_contains(filter_bytes: np.ndarray, num_bits: int, k: int, seed: int,
                      queries: np.ndarray, threads: int | None = None) -> np.ndarray:
     """Classic oracle lookups against `filter_bytes`, by query slices."""
     view = _holding(ClassicOracle(num_bits, k, seed), filter_bytes)
+    return lookups(view, queries, threads)
+
+
+def parquet_contains(filter_bytes: np.ndarray, num_bytes: int, queries: np.ndarray,
+                     threads: int | None = None) -> np.ndarray:
+    """Parquet split-block oracle lookups against `filter_bytes`, by query slices."""
+    view = _holding(ParquetOracle(num_bytes), filter_bytes)
     return lookups(view, queries, threads)
 
 
