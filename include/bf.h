@@ -116,11 +116,12 @@ typedef struct {
 } bf_mapping_t;
 
 /* Filter layouts (bf_info_t.layout).  bf_create makes the sectorized
- * layout; bf_variants.h creates the other two. */
+ * layout; bf_variants.h creates the next three, bf_parquet.h the last. */
 #define BF_LAYOUT_SECTORIZED 0       /* Sec. II-A-4 (s = 1: register-blocked) */
 #define BF_LAYOUT_CLASSIC 1          /* Sec. II-A-1: k positions over m bits */
 #define BF_LAYOUT_CACHE_SECTORIZED 2 /* Sec. II-A-5: one word per group of s/z */
 #define BF_LAYOUT_SECTORIZED_CHAINED 3 /* sectorized, chained pattern hashing (Sec. IV-B prior art) */
+#define BF_LAYOUT_PARQUET 4          /* sectorized 8 x 32, k = 8: the Parquet split-block format */
 
 typedef struct {
   uint64_t num_blocks;     /* 0 for the classic layout */

@@ -40,6 +40,7 @@ BF_LAYOUT_SECTORIZED = 0
 BF_LAYOUT_CLASSIC = 1
 BF_LAYOUT_CACHE_SECTORIZED = 2
 BF_LAYOUT_SECTORIZED_CHAINED = 3
+BF_LAYOUT_PARQUET = 4
 
 
 class bf_mapping_t(ctypes.Structure):
@@ -85,6 +86,14 @@ _lib.bf_create_csbf.argtypes = [_u64, _u32, _u32, _u32, _u32, _u64, ctypes.POINT
 _lib.bf_create_csbf.restype = _i32
 _lib.bf_create_chained.argtypes = [_u64, _u32, _u32, _u32, _u64, ctypes.POINTER(_vp)]
 _lib.bf_create_chained.restype = _i32
+_lib.bf_create_parquet.argtypes = [_u64, ctypes.POINTER(_vp)]
+_lib.bf_create_parquet.restype = _i32
+_lib.bf_create_parquet_in.argtypes = [_vp, _u64, ctypes.POINTER(_vp)]
+_lib.bf_create_parquet_in.restype = _i32
+_lib.bf_parquet_header.argtypes = [_u64, _vp, _u64, ctypes.POINTER(_u64)]
+_lib.bf_parquet_header.restype = _i32
+_lib.bf_parquet_parse_header.argtypes = [_vp, _u64, ctypes.POINTER(_u64), ctypes.POINTER(_u64)]
+_lib.bf_parquet_parse_header.restype = _i32
 _lib.bf_destroy.argtypes = [_vp]
 _lib.bf_destroy.restype = _i32
 _lib.bf_add.argtypes = [_vp, _vp, _u64, _vp]
@@ -249,6 +258,37 @@ def bf_create_chained(num_blocks: int, words_per_block: int, word_bits: int, k: 
     st = _lib.bf_create_chained(num_blocks, words_per_block, word_bits, k, seed & (2**64 - 1),
                                 ctypes.byref(h))
     return st, h
+
+
+def bf_create_parquet(num_bytes: int):
+    """Returns (status, handle) of a Parquet split-block filter (bf_parquet.h)."""
+    h = _vp()
+    st = _lib.bf_create_parquet(num_bytes, ctypes.byref(h))
+    return st, h
+
+
+def bf_create_parquet_in(d_words: int, num_bytes: int):
+    """Returns (status, handle) of a Parquet split-block filter over caller-owned words."""
+    h = _vp()
+    st = _lib.bf_create_parquet_in(d_words, num_bytes, ctypes.byref(h))
+    return st, h
+
+
+def bf_parquet_header(num_bytes: int):
+    """Returns (status, header bytes) of the format's bloom filter header."""
+    buf = (ctypes.c_uint8 * 32)()
+    n = _u64(0)
+    st = _lib.bf_parquet_header(num_bytes, buf, len(buf), ctypes.byref(n))
+    return st, bytes(buf[: n.value]) if st == BF_OK else b""
+
+
+def bf_parquet_parse_header(blob: bytes):
+    """Returns (status, num_bytes, header_len) of a bloom filter header at the
+    start of blob."""
+    buf = (ctypes.c_uint8 * max(len(blob), 1)).from_buffer_copy(bytes(blob) or b"\0")
+    nb, hl = _u64(0), _u64(0)
+    st = _lib.bf_parquet_parse_header(buf, len(blob), ctypes.byref(nb), ctypes.byref(hl))
+    return st, nb.value, hl.value
 
 
 def bf_destroy(f) -> int:
@@ -527,6 +567,38 @@ class CacheSectorizedFilter(_Filter):
         self.seed = seed
         st, h = bf_create_csbf(num_blocks, words_per_block, word_bits, groups, k, seed)
         self._adopt(st, h, "bf_create_csbf")
+
+
+class ParquetFilter(_Filter):
+    """Parquet split-block filter of num_bytes bytes (bf_create_parquet):
+    values are int64 / uint64 tensors (DOUBLE columns: their IEEE-754 bits)."""
+
+    def __init__(self, num_bytes: int):
+        st, h = bf_create_parquet(num_bytes)
+        self._adopt(st, h, "bf_create_parquet")
+
+    @classmethod
+    def from_parquet_blob(cls, blob: bytes) -> "ParquetFilter":
+        """A filter holding the bitset of a serialized bloom filter (the
+        format's header followed by the bitset, as a Parquet file stores it);
+        the copy is enqueued on the current stream."""
+        import torch
+
+        st, num_bytes, header_len = bf_parquet_parse_header(blob)
+        _check(st, "bf_parquet_parse_header")
+        if len(blob) < header_len + num_bytes:
+            raise ValueError("blob is shorter than its header says")
+        f = cls(num_bytes)
+        bits = torch.frombuffer(bytearray(blob[header_len:header_len + num_bytes]), dtype=torch.uint8)
+        f.load_words(bits.to(f"cuda:{f.device}"))
+        return f
+
+    def to_parquet_blob(self) -> bytes:
+        """The format's header followed by the bitset, read on the current
+        stream (waits for it)."""
+        st, header = bf_parquet_header(self.size_bytes())
+        _check(st, "bf_parquet_header")
+        return header + self.words().cpu().numpy().tobytes()
 
 
 class BatchPlan:

@@ -140,7 +140,12 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
                  void* stream) {
   if (f->layout != BF_LAYOUT_SECTORIZED)
     return variant_launch(f, op, keys, n, out, static_cast<hipStream_t>(stream));
-  ensure_registry();
+  const bool parquet = f->salts == kSaltsParquet;
+  if (parquet)
+    ensure_parquet_registry();
+  else
+    ensure_registry();
+  const Registry& reg = parquet ? parquet_registry() : registry();
   bf_mapping_t m = resolve_mapping(f, op, n);
   if (op == BF_OP_ADD && add_partitions(f, n))
     return partitioned_add(f, keys, n, static_cast<hipStream_t>(stream));
@@ -159,7 +164,7 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
     kt = 1;
     if (atom64 && !(f->word_bits == 32 && f->s >= 2)) atom64 = 0;
   }
-  const void* fn = registry().fn[registry_index(op, static_cast<int>(f->word_bits),
+  const void* fn = reg.fn[registry_index(op, static_cast<int>(f->word_bits),
                                                 static_cast<int>(f->s), kidx,
                                                 static_cast<int>(m.lanes_per_key),
                                                 static_cast<int>(m.words_per_lane),
@@ -492,7 +497,7 @@ bf_status bf_info(const bf_filter* f, bf_info_t* out) {
   i.d_words = f->d_words;
   i.mapping[BF_OP_ADD] = resolve_mapping(f, BF_OP_ADD, ~0ull);
   i.mapping[BF_OP_CONTAINS] = resolve_mapping(f, BF_OP_CONTAINS, ~0ull);
-  i.layout = f->layout;
+  i.layout = f->salts == kSaltsParquet ? BF_LAYOUT_PARQUET : f->layout;
   i.groups = f->groups;
   i.num_bits = f->num_bits;
   *out = i;

@@ -391,7 +391,8 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   if (f0 == nullptr) return BF_EINVAL;
   for (uint32_t i = 0; i < nfilters; ++i) {
     const bf_filter* f = filters[i];
-    if (f != nullptr && f->layout != BF_LAYOUT_SECTORIZED) return BF_EUNSUPPORTED;
+    if (f != nullptr && (f->layout != BF_LAYOUT_SECTORIZED || f->salts != kSaltsPaper))
+      return BF_EUNSUPPORTED;
     if (f == nullptr || f->s != f0->s || f->word_bits != f0->word_bits || f->k != f0->k ||
         f->device != f0->device)
       return BF_EINVAL;

@@ -72,6 +72,12 @@ __device__ __forceinline__ constexpr uint32_t salt() {
   return kSalts.a[J];
 }
 
+// The salt table as a type, for pattern generators that take it as a
+// template argument (another table gives another filter format).
+struct PaperSalts {
+  static constexpr uint32_t at(int j) { return kSalts.a[j]; }
+};
+
 // A few values are checked at compile time against the derivation above
 // (the salts are odd by construction).
 static_assert((kSalts.a[0] & kSalts.a[31] & 1u) == 1u, "salts are odd");

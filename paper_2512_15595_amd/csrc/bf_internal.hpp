@@ -11,6 +11,11 @@
 #include "../../include/bf.h"
 
 namespace bfhip {
+// Pattern multipliers of a sectorized filter: the derived salts of
+// bf_hash.hpp, or the Parquet split-block format's constants (bf_parquet.h).
+constexpr uint32_t kSaltsPaper = 0;
+constexpr uint32_t kSaltsParquet = 1;
+
 // Stream order of the bf.h calls on one filter (ordered_call below).
 // Every call records the filter's last use on its stream.  A partitioned add
 // loads whole chunks into LDS and stores them back, so it first waits for
@@ -44,6 +49,7 @@ struct bf_filter {
   bool owns_words;          // false for bf_create_in
   bool pooled_words;        // words from the device's filter pool (freed in stream order)
   uint32_t groups;          // cache-sectorized z, else 0
+  uint32_t salts;           // sectorized pattern multipliers: bfhip::kSaltsPaper or kSaltsParquet
   uint64_t num_bits;        // nbytes * 8
   bfhip::FilterOrder order;
 };

@@ -119,18 +119,20 @@ struct LanePatterns {
   uint32_t salt[kSteps][PHI][kSlots];
   uint32_t q;
 
-  __device__ __forceinline__ explicit LanePatterns(uint32_t lane_rank) : q(lane_rank) {
+  // SALTS::at(j) is salt j (PaperSalts: the derivation of bf_hash.hpp).
+  template <typename SALTS = PaperSalts>
+  __device__ __forceinline__ explicit LanePatterns(uint32_t lane_rank, SALTS = SALTS{}) : q(lane_rank) {
 #pragma unroll
     for (int st = 0; st < kSteps; ++st)
 #pragma unroll
       for (int f = 0; f < PHI; ++f)
 #pragma unroll
         for (int i = 0; i < kSlots; ++i) {
-          uint32_t v = kSalts.a[st * THETA * PHI + f + i * S_WORDS];
+          uint32_t v = SALTS::at(st * THETA * PHI + f + i * S_WORDS);
 #pragma unroll
           for (int r = 1; r < THETA; ++r)
             v = (lane_rank == static_cast<uint32_t>(r))
-                    ? kSalts.a[st * THETA * PHI + r * PHI + f + i * S_WORDS]
+                    ? SALTS::at(st * THETA * PHI + r * PHI + f + i * S_WORDS)
                     : v;
           salt[st][f][i] = v;
         }
@@ -336,8 +338,7 @@ __device__ __forceinline__ void contains_tile(const FilterView& fv, const uint64
 // aligned keys and KT-byte aligned results.
 // ---------------------------------------------------------------------------
 template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
-__global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
-  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+__device__ __forceinline__ void add_keys(const BfArgs& a, const LanePatterns<W, S_WORDS, K, THETA, PHI>& lp) {
   const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
   const uint64_t tile = static_cast<uint64_t>(blockDim.x) * KT;
   const uint64_t stride = tile * gridDim.x;
@@ -349,8 +350,8 @@ __global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
 }
 
 template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT>
-__global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
-  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+__device__ __forceinline__ void contains_keys(const BfArgs& a,
+                                              const LanePatterns<W, S_WORDS, K, THETA, PHI>& lp) {
   const FilterView fv{a.words, a.hash_init, a.nb_lo, a.nb_hi_mask};
   const uint64_t tile = static_cast<uint64_t>(blockDim.x) * KT;
   const uint64_t stride = tile * gridDim.x;
@@ -359,6 +360,18 @@ __global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
     contains_tile<W, S_WORDS, K, THETA, PHI, KT>(fv, a.keys + base, a.out + base, count,
                                                  count == tile, a.k, lp);
   }
+}
+
+template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT, bool ATOM64>
+__global__ __launch_bounds__(kBlockThreads) void bf_add_kernel(BfArgs a) {
+  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+  add_keys<W, S_WORDS, K, THETA, PHI, KT, ATOM64>(a, lp);
+}
+
+template <typename W, int S_WORDS, int K, int THETA, int PHI, int KT>
+__global__ __launch_bounds__(kBlockThreads) void bf_contains_kernel(BfArgs a) {
+  const LanePatterns<W, S_WORDS, K, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1));
+  contains_keys<W, S_WORDS, K, THETA, PHI, KT>(a, lp);
 }
 
 }  // namespace bfhip

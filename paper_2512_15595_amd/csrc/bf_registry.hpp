@@ -79,4 +79,11 @@ void register_u64_s4(Registry&);
 void register_u64_s8(Registry&);
 void register_u64_s16(Registry&);
 
+// The same table for the Parquet split-block filter (bf_parquet.h): the
+// 32-bit, s = 8, k = 8 slots only (add and lookup for every mapping, the
+// partitioned kernels in the single-filter slots; no batched kernels).
+Registry& parquet_registry();
+void ensure_parquet_registry();
+void register_parquet(Registry&);
+
 }  // namespace bfhip

@@ -1,7 +1,8 @@
 """The Parquet split-block Bloom filter (the Arrow / Parquet-compatible
 configuration of the paper's Sec. I and Sec. VI) on the CPU: the oracle's
 bitset is pinned to the bitsets Apache Arrow (pyarrow, an independent
-implementation of the format) writes into Parquet files.  No GPU needed.
+implementation of the format) writes into Parquet files, and the library's
+host-only header functions to the headers it writes.  No GPU needed.
 """
 from __future__ import annotations
 
@@ -143,3 +144,55 @@ def test_oracle_rejects_bad_sizes():
     for nb in (0, 16, 33, 48 + 1):
         with pytest.raises(ValueError):
             oracle.ParquetOracle(nb)
+
+
+# ---- the library's host-only header functions (no GPU call) -------------------
+
+def _bf():
+    from paper_2512_15595_amd import bf
+
+    return bf
+
+
+@pytest.mark.parametrize("n,ndv,fpp,seed", CASES)
+def test_library_header_equals_arrow(n, ndv, fpp, seed):
+    bf = _bf()
+    rng = np.random.default_rng(seed)
+    (blob,) = arrow_blobs(pa.array(rng.integers(0, 2**40, size=n, dtype=np.int64)), ndv, fpp)
+    num_bytes, _ = split(blob)
+    st, got_nb, header_len = bf.bf_parquet_parse_header(blob)
+    assert st == bf.BF_OK
+    assert got_nb == num_bytes and header_len + num_bytes == len(blob)
+    st, header = bf.bf_parquet_header(num_bytes)
+    assert st == bf.BF_OK and header == blob[:header_len]
+
+
+def test_library_header_round_trip_and_errors():
+    bf = _bf()
+    for nb in (32, 96, 1 << 20, 128 << 20, (1 << 31) - 32):
+        st, h = bf.bf_parquet_header(nb)
+        assert st == bf.BF_OK and len(h) <= 20
+        assert bf.bf_parquet_parse_header(h + b"\x00" * 8) == (bf.BF_OK, nb, len(h))
+    for nb in (0, 16, 33, 1 << 31):
+        assert bf.bf_parquet_header(nb)[0] == bf.BF_EINVAL
+    st, h = bf.bf_parquet_header(2048)
+    for cut in range(len(h)):  # every truncation is malformed
+        assert bf.bf_parquet_parse_header(h[:cut])[0] == bf.BF_EINVAL
+    # another algorithm / hash / compression (field 2 of the union) is not this format
+    other = bytearray(h)
+    other[h.index(0x1C) + 1] = 0x2C
+    assert bf.bf_parquet_parse_header(bytes(other))[0] == bf.BF_EUNSUPPORTED
+    # a field the format might add later (id 5, binary) is skipped
+    extended = h[:-1] + bytes([0x18, 3]) + b"abc" + b"\x00"
+    assert bf.bf_parquet_parse_header(extended) == (bf.BF_OK, 2048, len(extended))
+    # numBytes not a multiple of 32
+    assert bf.bf_parquet_parse_header(bytes([0x15, 2 * 40]) + h[2:])[0] == bf.BF_EINVAL
+
+
+def test_library_rejects_bad_parquet_sizes_without_gpu():
+    bf = _bf()
+    for nb in (0, 16, 33, (1 << 37) + 32):
+        st, _ = bf.bf_create_parquet(nb)
+        assert st == bf.BF_EINVAL
+        st, _ = bf.bf_create_parquet_in(256, nb)
+        assert st == bf.BF_EINVAL
