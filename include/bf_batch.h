@@ -64,9 +64,9 @@ typedef struct {
 /* Plans one batched operation (op = BF_OP_ADD or BF_OP_CONTAINS) over
  * filters[0..nfilters).  h_offsets is a host array of nfilters + 1
  * non-decreasing key offsets; d_out is required for contains and ignored for
- * add.  Every filter must have the sectorized layout of bf.h (not the
- * Parquet configuration of bf_parquet.h), with one (s, S, k) and one device
- * (else BF_EUNSUPPORTED / BF_EINVAL).  On success
+ * add.  Every filter must have the sectorized layout of bf.h, with one
+ * (s, S, k), one device and one salt table -- all of them Parquet filters
+ * (bf_parquet.h) or none (else BF_EUNSUPPORTED / BF_EINVAL).  On success
  * *out receives the plan. */
 bf_status bf_batch_plan(int op, bf_filter *const *filters, uint32_t nfilters,
                         const uint64_t *d_keys, const uint64_t *h_offsets,

@@ -29,8 +29,10 @@
  * mapping of the 8 x 32-bit, k = 8 sectorized layout applies, and adds
  * choose between the direct and the partitioned construction by the same
  * measured crossover.  bf_info reports layout BF_LAYOUT_PARQUET.  Batched
- * plans (bf_batch.h) and servers (bf_serve.h) do not accept them
- * (BF_EUNSUPPORTED).
+ * plans (bf_batch.h) and servers (bf_serve.h) take them -- the pruning shape
+ * of a Parquet scan, a few values looked up in the filter of every row
+ * group, is one batched lookup -- provided every filter of the plan or
+ * server is a Parquet filter (else BF_EINVAL).
  */
 #ifndef BF_PARQUET_H
 #define BF_PARQUET_H

@@ -77,8 +77,8 @@ typedef struct {
  * starts its scheduler thread.  cfg == NULL takes defaults (16 GiB budget,
  * 16 launches in flight, 8 streams, coalescing below 65,536 keys, up to 256
  * requests or 16,384 tiles per shared launch).  The filters must have the
- * sectorized layout of bf.h (not the Parquet configuration of
- * bf_parquet.h), one (s, S, k) and one device (else BF_EUNSUPPORTED /
+ * sectorized layout of bf.h, one (s, S, k), one device and one salt table --
+ * all of them Parquet filters (bf_parquet.h) or none (else BF_EUNSUPPORTED /
  * BF_EINVAL). */
 bf_status bf_server_create(bf_filter *const *filters, uint32_t nfilters,
                            const bf_server_config_t *cfg, bf_server **out);

@@ -140,12 +140,7 @@ bf_status launch(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t
                  void* stream) {
   if (f->layout != BF_LAYOUT_SECTORIZED)
     return variant_launch(f, op, keys, n, out, static_cast<hipStream_t>(stream));
-  const bool parquet = f->salts == kSaltsParquet;
-  if (parquet)
-    ensure_parquet_registry();
-  else
-    ensure_registry();
-  const Registry& reg = parquet ? parquet_registry() : registry();
+  const Registry& reg = kernel_table(f->salts == kSaltsParquet);
   bf_mapping_t m = resolve_mapping(f, op, n);
   if (op == BF_OP_ADD && add_partitions(f, n))
     return partitioned_add(f, keys, n, static_cast<hipStream_t>(stream));

@@ -391,10 +391,9 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   if (f0 == nullptr) return BF_EINVAL;
   for (uint32_t i = 0; i < nfilters; ++i) {
     const bf_filter* f = filters[i];
-    if (f != nullptr && (f->layout != BF_LAYOUT_SECTORIZED || f->salts != kSaltsPaper))
-      return BF_EUNSUPPORTED;
+    if (f != nullptr && f->layout != BF_LAYOUT_SECTORIZED) return BF_EUNSUPPORTED;
     if (f == nullptr || f->s != f0->s || f->word_bits != f0->word_bits || f->k != f0->k ||
-        f->device != f0->device)
+        f->device != f0->device || f->salts != f0->salts)
       return BF_EINVAL;
     if (h_offsets[i + 1] < h_offsets[i]) return BF_EINVAL;
   }
@@ -403,8 +402,7 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
     return BF_EINVAL;
   if (op == BF_OP_CONTAINS && nkeys > 0 && d_out == nullptr) return BF_EINVAL;
 
-  ensure_registry();
-  const void* fn = registry().batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
+  const void* fn = kernel_table(f0->salts == kSaltsParquet).batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
                                                    static_cast<int>(f0->s), k_index(f0->k))];
   if (fn == nullptr) return BF_EUNSUPPORTED;
 

@@ -55,7 +55,7 @@ constexpr MapSpec batch_map() {
   }
 }
 
-template <typename W, int S_WORDS, int K, int OP, int CLS>
+template <typename W, int S_WORDS, int K, int OP, int CLS, typename SALTS>
 __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchTile& t,
                                            const BatchFilter& f, const FilterView& fv) {
   constexpr MapSpec m = batch_map<W, S_WORDS, K, OP, CLS>();
@@ -64,7 +64,7 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchTile& 
   constexpr int kKt = static_cast<int>(m.kt);
   static_assert(kTheta * kPhi <= S_WORDS && kTheta <= 16, "tuned mapping fits the block");
   constexpr bool kAtom64 = OP == 0 && sizeof(W) == 4 && kPhi >= 2 && m.atomic_bits == 64;
-  const LanePatterns<W, S_WORDS, K, kTheta, kPhi> lp((threadIdx.x & 63u) & (kTheta - 1));
+  const LanePatterns<W, S_WORDS, K, kTheta, kPhi> lp((threadIdx.x & 63u) & (kTheta - 1), SALTS{});
   const uint32_t count = t.meta & kTileCountMask;
   const bool vec_ok = (t.meta & kTileVecBit) != 0;
   if constexpr (OP == 0) {
@@ -76,19 +76,26 @@ __device__ __forceinline__ void batch_tile(const BatchArgs& a, const BatchTile& 
   }
 }
 
-template <typename W, int S_WORDS, int K, int OP>
-__global__ __launch_bounds__(kBlockThreads) void bf_batch_kernel(BatchArgs a) {
+// The tile walk, for the pattern multipliers SALTS (bf_hash.hpp's salts,
+// or another filter format's table).
+template <typename W, int S_WORDS, int K, int OP, typename SALTS>
+__device__ __forceinline__ void batch_tiles(const BatchArgs& a) {
   for (uint64_t i = blockIdx.x; i < a.ntiles; i += gridDim.x) {
     const BatchTile t = a.tiles[i];
     if ((t.meta & kTileCountMask) == 0) continue;  // padding slot
     const BatchFilter f = a.filters[t.filter];
     const FilterView fv{f.words, f.hash_init, f.nb_lo, f.nb_hi_mask};
     switch ((t.meta >> kTileClassShift) & 3u) {
-      case 0: batch_tile<W, S_WORDS, K, OP, 0>(a, t, f, fv); break;
-      case 1: batch_tile<W, S_WORDS, K, OP, 1>(a, t, f, fv); break;
-      default: batch_tile<W, S_WORDS, K, OP, 2>(a, t, f, fv); break;
+      case 0: batch_tile<W, S_WORDS, K, OP, 0, SALTS>(a, t, f, fv); break;
+      case 1: batch_tile<W, S_WORDS, K, OP, 1, SALTS>(a, t, f, fv); break;
+      default: batch_tile<W, S_WORDS, K, OP, 2, SALTS>(a, t, f, fv); break;
     }
   }
+}
+
+template <typename W, int S_WORDS, int K, int OP>
+__global__ __launch_bounds__(kBlockThreads) void bf_batch_kernel(BatchArgs a) {
+  batch_tiles<W, S_WORDS, K, OP, PaperSalts>(a);
 }
 
 }  // namespace bfhip

@@ -1,6 +1,7 @@
 // Kernel variants of the Parquet split-block filter (bf_parquet.h): every
 // mapping of the sectorized 8 x 32-bit, k = 8 layout, in the same registry
-// slots, and the three partitioned-construction kernels.
+// slots, the persistent batched kernels, and the partitioned-construction
+// kernels (single-filter and multi-filter first pass).
 #include <utility>
 
 #include "bf_parquet.hpp"
@@ -46,9 +47,15 @@ void register_parquet(Registry& r) {
   register_phi<2>(r);
   register_phi<4>(r);
   register_phi<8>(r);
+  r.batch_fn[batch_index(kOpAdd, 32, kParquetWords, kIdxK)] =
+      reinterpret_cast<const void*>(&parquet_batch_kernel<kOpAdd>);
+  r.batch_fn[batch_index(kOpContains, 32, kParquetWords, kIdxK)] =
+      reinterpret_cast<const void*>(&parquet_batch_kernel<kOpContains>);
   const int slot = batch_index(kOpAdd, 32, kParquetWords, kIdxK);
   r.part1_fn[slot] =
       reinterpret_cast<const void*>(&part_scatter1_kernel<uint32_t, kParquetWords, kParquetK, kZParquet>);
+  r.part1_multi_fn[slot] = reinterpret_cast<const void*>(
+      &part_scatter1_kernel<uint32_t, kParquetWords, kParquetK, kZParquet, true>);
   r.part2_fn[slot] =
       reinterpret_cast<const void*>(&part_scatter2_kernel<uint32_t, kParquetWords, kParquetK, kZParquet>);
   r.apply_fn[slot] =

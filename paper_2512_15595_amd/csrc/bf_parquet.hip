@@ -23,6 +23,15 @@ void ensure_parquet_registry() {
   std::call_once(once, [] { register_parquet(parquet_registry()); });
 }
 
+const Registry& kernel_table(bool parquet) {
+  if (parquet) {
+    ensure_parquet_registry();
+    return parquet_registry();
+  }
+  ensure_registry();
+  return registry();
+}
+
 namespace {
 
 constexpr uint64_t kBlockBytes = 32;  // eight 32-bit words

@@ -16,6 +16,7 @@
 
 #include <stdint.h>
 
+#include "bf_batch_kernels.hpp"
 #include "bf_hash.hpp"
 #include "bf_kernels.hpp"
 #include "bf_partition.hpp"
@@ -59,6 +60,12 @@ __global__ __launch_bounds__(kBlockThreads) void parquet_contains_kernel(BfArgs 
   const LanePatterns<uint32_t, kParquetWords, kParquetK, THETA, PHI> lp((threadIdx.x & 63u) & (THETA - 1),
                                                                        ParquetSalts{});
   contains_keys<uint32_t, kParquetWords, kParquetK, THETA, PHI, KT>(a, lp);
+}
+
+// The persistent kernel of batched plans and servers over Parquet filters.
+template <int OP>
+__global__ __launch_bounds__(kBlockThreads) void parquet_batch_kernel(BatchArgs a) {
+  batch_tiles<uint32_t, kParquetWords, kParquetK, OP, ParquetSalts>(a);
 }
 
 }  // namespace bfhip

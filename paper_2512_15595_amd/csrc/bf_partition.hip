@@ -139,14 +139,9 @@ PartKernels part_kernels(const bf_filter* f) {
   }
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
-  if (f->salts == kSaltsParquet) {  // single-filter kernels only
-    ensure_parquet_registry();
-    const Registry& r = parquet_registry();
-    return PartKernels{r.part1_fn[idx], nullptr, r.part2_fn[idx], r.apply_fn[idx], kScatter1Threads};
-  }
-  ensure_registry();
-  return PartKernels{registry().part1_fn[idx], registry().part1_multi_fn[idx], registry().part2_fn[idx],
-                     registry().apply_fn[idx], kScatter1Threads};
+  const Registry& r = kernel_table(f->salts == kSaltsParquet);
+  return PartKernels{r.part1_fn[idx], r.part1_multi_fn[idx], r.part2_fn[idx], r.apply_fn[idx],
+                     kScatter1Threads};
 }
 
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k,

@@ -86,4 +86,8 @@ Registry& parquet_registry();
 void ensure_parquet_registry();
 void register_parquet(Registry&);
 
+// The filled table of a filter's pattern multipliers: the Parquet format's
+// (parquet) or the derived salts.
+const Registry& kernel_table(bool parquet);
+
 }  // namespace bfhip

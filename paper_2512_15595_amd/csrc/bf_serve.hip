@@ -403,10 +403,9 @@ bf_status bf_server_create(bf_filter* const* filters, uint32_t nfilters,
   if (f0 == nullptr) return BF_EINVAL;
   for (uint32_t i = 0; i < nfilters; ++i) {
     const bf_filter* f = filters[i];
-    if (f != nullptr && (f->layout != BF_LAYOUT_SECTORIZED || f->salts != kSaltsPaper))
-      return BF_EUNSUPPORTED;
+    if (f != nullptr && f->layout != BF_LAYOUT_SECTORIZED) return BF_EUNSUPPORTED;
     if (f == nullptr || f->s != f0->s || f->word_bits != f0->word_bits || f->k != f0->k ||
-        f->device != f0->device)
+        f->device != f0->device || f->salts != f0->salts)
       return BF_EINVAL;
   }
   bf_server_config_t c{};
@@ -425,7 +424,7 @@ bf_status bf_server_create(bf_filter* const* filters, uint32_t nfilters,
   if (c.coalesce_max_keys > 0 && (c.coalesce_max_requests == 0 || c.coalesce_max_tiles == 0))
     return BF_EINVAL;
 
-  ensure_registry();
+  const Registry& reg = kernel_table(f0->salts == kSaltsParquet);
   bf_server* s = new (std::nothrow) bf_server();
   if (s == nullptr) return BF_ENOMEM;
   s->filters.assign(filters, filters + nfilters);
@@ -433,7 +432,7 @@ bf_status bf_server_create(bf_filter* const* filters, uint32_t nfilters,
   s->device = f0->device;
   s->deps.resize(nfilters);
   for (int op = 0; op < 2; ++op)
-    s->batch_fn[op] = registry().batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
+    s->batch_fn[op] = reg.batch_fn[batch_index(op, static_cast<int>(f0->word_bits),
                                                       static_cast<int>(f0->s), k_index(f0->k))];
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, s->device) == hipSuccess && prop.multiProcessorCount > 0)

@@ -107,20 +107,125 @@ def test_parquet_noalloc_and_strategy_agree():
     assert np.array_equal(wa, ref.bytes) and np.array_equal(wb, ref.bytes)
 
 
-def test_parquet_is_refused_by_plans_and_servers():
+def _row_groups(nfilters, total, dense=(), seed=31):
+    """Filters of a Parquet scan's row groups: power-of-two sizes 1 KiB ..
+    1 MiB, Zipf-skewed value counts, plus `dense` (num_bytes, values) ones."""
+    g = workloads.rng(seed)
+    sizes = [1 << int(e) for e in g.integers(10, 21, size=nfilters)] + [nb for nb, _ in dense]
+    counts = list(workloads.zipf_counts(nfilters, total, 1.1, 0, total // 4, seed + 1)) + [n for _, n in dense]
+    offsets = np.zeros(len(sizes) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    values = _values(int(offsets[-1]), seed + 2)
+    queries = workloads.mix(values, _values(values.size, seed + 3), 0.5, seed + 4)
+    return sizes, offsets, values, queries
+
+
+@pytest.mark.parametrize("mode", ["launch", "launch_per_filter"])
+def test_parquet_batched_plans_equal_oracle(mode):
+    """A plan over row-group filters (and three dense ones, which take the
+    multi-filter partitioned construction) with the format's salts."""
+    bf = _bf()
+    sizes, offsets, values, queries = _row_groups(200, 1 << 18, dense=[(16 << 20, 2_000_000)] * 3)
+    filters = [bf.ParquetFilter(nb) for nb in sizes]
+    d_v = to_device(values)
+    d_q = to_device(queries)
+    d_out = torch.full((queries.size,), 7, dtype=torch.uint8, device="cuda")
+    add = bf.BatchPlan(bf.BF_OP_ADD, filters, d_v, offsets)
+    con = bf.BatchPlan(bf.BF_OP_CONTAINS, filters, d_q, offsets, d_out)
+    try:
+        log(f"parquet plans ({mode}): {len(filters)} filters, {values.size} values")
+        if mode == "launch":
+            assert add.info().strategy == bf.BF_STRATEGY_PARTITIONED
+        getattr(add, mode)()
+        getattr(con, mode)()
+        words = [f.words().cpu().numpy() for f in filters]
+        out = d_out.cpu().numpy()
+        torch.cuda.synchronize()
+    finally:
+        add.close()
+        con.close()
+        for f in filters:
+            f.close()
+    want_out = np.zeros(queries.size, dtype=np.uint8)
+    for i, nb in enumerate(sizes):
+        a, b = offsets[i], offsets[i + 1]
+        ref = oracle.ParquetOracle(nb)
+        ref.add(values[a:b])
+        assert np.array_equal(words[i], ref.bytes), f"filter {i} ({nb} B)"
+        want_out[a:b] = ref.contains(queries[a:b])
+    assert np.array_equal(out, want_out)
+
+
+def test_parquet_plans_and_servers_take_one_salt_table():
     bf = _bf()
     f = bf.ParquetFilter(4096)
     g = bf.BloomFilter(4096 // 32, 8, 32, 8, 0)
     keys = to_device(_values(100, 7))
     try:
         st, _ = bf.bf_batch_plan(bf.BF_OP_ADD, [f.handle, g.handle], keys.data_ptr(), [0, 50, 100])
-        assert st == bf.BF_EUNSUPPORTED
+        assert st == bf.BF_EINVAL
         with pytest.raises(bf.BfError) as e:
-            bf.Server([f])
-        assert e.value.status == bf.BF_EUNSUPPORTED
+            bf.Server([f, g])
+        assert e.value.status == bf.BF_EINVAL
     finally:
         f.close()
         g.close()
+
+
+def test_parquet_served_requests_equal_sequential_oracle():
+    """Interleaved adds and lookups on row-group filters through the
+    server (coalesced small requests, and adds large enough for the
+    partitioned construction), against the oracle replaying them in order."""
+    bf = _bf()
+    g = workloads.rng(41)
+    sizes = [64 << 10, 256 << 10, 1 << 20, 2 << 20, 4 << 20]
+    nreq = 200
+    ops = np.where(g.random(nreq) < 0.15, 0, 1)
+    filt = g.integers(0, len(sizes), size=nreq)
+    ns = np.exp(np.log(50) + g.random(nreq) * (np.log(40_000) - np.log(50))).astype(np.int64)
+    ns[:3] = 2_500_000                      # dense adds: partitioned
+    ops[:3] = 0
+    filt[:3] = [2, 3, 4]
+    keys = _values(int(ns.sum()), 42)
+    starts = np.concatenate([[0], np.cumsum(ns)])
+    for i in range(nreq):                   # half of each lookup's values were added earlier
+        if ops[i] == 1 and i > 0:
+            prev = np.flatnonzero((ops[:i] == 0) & (filt[:i] == filt[i]))
+            if prev.size:
+                j = prev[-1]
+                m = min(ns[i] // 2, ns[j])
+                keys[starts[i]:starts[i] + m] = keys[starts[j]:starts[j] + m]
+    arrivals = np.cumsum(g.exponential(20_000, size=nreq)).astype(np.int64)
+    refs = [oracle.ParquetOracle(nb) for nb in sizes]
+    want = np.zeros(keys.size, dtype=np.uint8)
+    for i in range(nreq):
+        a, b = starts[i], starts[i + 1]
+        if ops[i] == 0:
+            refs[filt[i]].add(keys[a:b])
+        else:
+            want[a:b] = refs[filt[i]].contains(keys[a:b])
+    filters = [bf.ParquetFilter(nb) for nb in sizes]
+    d_keys = to_device(keys)
+    d_out = torch.full((keys.size,), 9, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    srv = bf.Server(filters)
+    try:
+        log(f"parquet server: {nreq} requests, {keys.size} values")
+        kp = [d_keys.data_ptr() + 8 * int(starts[i]) for i in range(nreq)]
+        op_ptr = [d_out.data_ptr() + int(starts[i]) if ops[i] == 1 else 0 for i in range(nreq)]
+        res = srv.replay(srv.requests(ops, filt, kp, ns, op_ptr, arrivals))
+        torch.cuda.synchronize()
+        out = d_out.cpu().numpy()
+        words = [f.words().cpu().numpy() for f in filters]
+    finally:
+        srv.close()
+        for f in filters:
+            f.close()
+    assert all(r.status == 0 for r in res)
+    mask = np.repeat(ops == 1, ns)
+    assert np.array_equal(out[mask], want[mask])
+    for i, r in enumerate(refs):
+        assert np.array_equal(words[i], r.bytes), f"filter {i}"
 
 
 # ---- the format's largest filter, every byte and every lookup ----------------
