@@ -879,6 +879,105 @@ def run_layouts(args) -> dict:
     }
 
 
+def run_parquet(args) -> dict:
+    """The Parquet split-block filter (include/bf_parquet.h).  Bulk rates on
+    the format's largest filter (128 MiB; 2^27 values, lookups at 50 % hits),
+    and the pruning step of a Parquet scan: `literals` values looked up in
+    the filter of every row group (1 MiB filters of 2^19 values each, the
+    size a writer picks for that many distinct values at 1 % FPR), as one
+    batched graph launch against one launch per row group."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2512_15595_amd import bf as bfmod
+    from paper_2512_15595_amd.bf import BF_OP_ADD, BF_OP_CONTAINS, BatchPlan, ParquetFilter
+
+    lib = ctypes.CDLL(bfmod.LIB_PATH)
+    vp, u64, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32
+    lib.bfb_fill_splitmix64.argtypes = [vp, u64, u64, u64, vp]
+    lib.bfb_fill_mixed_queries.argtypes = [vp, u64, u64, u64, u32, u64, u64, u32, u64, vp]
+    stream = torch.cuda.current_stream().cuda_stream
+    reps = max(3, args.steps)
+
+    def median_ms(fn, before=None):
+        ts = []
+        for _ in range(reps):
+            if before is not None:
+                before()
+            with Timer(torch) as t:
+                fn()
+            torch.cuda.synchronize()
+            ts.append(t.ms())
+        return float(np.median(ts))
+
+    nbytes, n = 128 << 20, 1 << 27
+    log(f"[bench] parquet: {n} values into the format's largest filter (128 MiB)")
+    vals = torch.empty(n, dtype=torch.int64, device="cuda")
+    qs = torch.empty(n, dtype=torch.int64, device="cuda")
+    assert lib.bfb_fill_splitmix64(vals.data_ptr(), n, 301, 0, stream) == 0
+    assert lib.bfb_fill_mixed_queries(qs.data_ptr(), n, 301, 0, n, 302, 0, 1 << 31, 303, stream) == 0
+    out = torch.empty(n, dtype=torch.uint8, device="cuda")
+    f = ParquetFilter(nbytes)
+    f.add(vals)
+    f.contains(qs, out)
+    torch.cuda.synchronize()
+    add_ms = median_ms(lambda: f.add(vals), before=f.clear)
+    con_ms = median_ms(lambda: f.contains(qs, out))
+    strategy = f.add_strategy(n)
+    f.close()
+    del vals, qs, out
+
+    rgs, per_rg, lits = 1024, 1 << 19, 16
+    log(f"[bench] parquet pruning: {rgs} row-group filters of 1 MiB, {lits} literals each")
+    filters = [ParquetFilter(1 << 20) for _ in range(rgs)]
+    vals = torch.empty(rgs * per_rg, dtype=torch.int64, device="cuda")
+    assert lib.bfb_fill_splitmix64(vals.data_ptr(), vals.numel(), 311, 0, stream) == 0
+    # a literal is a value of its row group with probability 1/16
+    qs = torch.empty(rgs * lits, dtype=torch.int64, device="cuda")
+    for i in range(rgs):
+        assert lib.bfb_fill_mixed_queries(qs[i * lits:].data_ptr(), lits, 311, i * per_rg, per_rg, 312,
+                                          i * lits, 1 << 28, 313 + i, stream) == 0
+    offs_v = [i * per_rg for i in range(rgs + 1)]
+    offs_q = [i * lits for i in range(rgs + 1)]
+    out_g = torch.zeros(rgs * lits, dtype=torch.uint8, device="cuda")
+    out_p = torch.zeros(rgs * lits, dtype=torch.uint8, device="cuda")
+    build = BatchPlan(BF_OP_ADD, filters, vals, offs_v)
+    prune = BatchPlan(BF_OP_CONTAINS, filters, qs, offs_q, out_g)
+    prune_p = BatchPlan(BF_OP_CONTAINS, filters, qs, offs_q, out_p)
+    build.launch()
+    prune.launch()
+    prune_p.launch_per_filter()
+    torch.cuda.synchronize()
+    build_ms = median_ms(build.launch, before=lambda: [g.clear() for g in filters])
+    graph_ms = median_ms(prune.launch)
+    per_filter_ms = median_ms(prune_p.launch_per_filter)
+    hits = out_g.view(rgs, lits).any(dim=1)
+    res = {
+        "workload": "parquet_sbbf_128MiB_and_pruning_1024_row_groups_1MiB",
+        "filter_bytes": nbytes, "values": n,
+        "add_gkeys_s": round(n / (add_ms * 1e-3) / 1e9, 3),
+        "contains_gkeys_s": round(n / (con_ms * 1e-3) / 1e9, 3),
+        "add_strategy": "partitioned" if strategy == bfmod.BF_STRATEGY_PARTITIONED else "direct",
+        "ms": {"add": round(add_ms, 4), "contains": round(con_ms, 4)},
+        "pruning": {
+            "row_groups": rgs, "values_per_row_group": per_rg, "literals_per_row_group": lits,
+            "build_gkeys_s": round(rgs * per_rg / (build_ms * 1e-3) / 1e9, 3),
+            "graph_us": round(graph_ms * 1e3, 2), "per_filter_us": round(per_filter_ms * 1e3, 2),
+            "speedup_vs_per_filter": round(per_filter_ms / graph_ms, 2),
+            "row_groups_per_s": round(rgs / (graph_ms * 1e-3), 1),
+            "row_groups_kept": int(hits.sum().item()),
+            "results_equal": bool(torch.equal(out_g, out_p)),
+        },
+    }
+    for plan in (build, prune, prune_p):
+        plan.close()
+    for g in filters:
+        g.close()
+    return res
+
+
 def run_bounds(args) -> dict:
     """The random-access microbenchmarks versus footprint (1 MiB .. 4 GiB):
     random aligned 8-byte and 32-byte reads (one and two lanes per segment),
@@ -923,7 +1022,7 @@ def main() -> int:
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-coalesce-keys", type=int, default=65536)
     ap.add_argument("--workload",
-                    choices=["dram", "batched", "serve", "cache", "breakdown", "layouts", "bounds"],
+                    choices=["dram", "batched", "serve", "cache", "breakdown", "layouts", "bounds", "parquet"],
                     default="dram")
     ap.add_argument("--bounds-log2-bytes", type=int, nargs="+", default=[20, 22, 24, 26, 28, 30, 32])
     ap.add_argument("--layouts-keys", type=int, default=10**9)
@@ -954,6 +1053,7 @@ def main() -> int:
     ap.add_argument("--no-direct-add", action="store_true", help="skip the direct-construction timing")
     ap.add_argument("--no-serve", action="store_true", help="skip the served leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched leg")
+    ap.add_argument("--no-parquet", action="store_true", help="skip the Parquet split-block leg")
     ap.add_argument("--line-serve-requests", type=int, default=2000,
                     help="requests per load in the served leg of the benchmark line")
     args = ap.parse_args()
@@ -989,6 +1089,9 @@ def main() -> int:
         return 0
     if args.workload == "bounds":
         print(json.dumps(run_bounds(args)), flush=True)
+        return 0
+    if args.workload == "parquet":
+        print(json.dumps(run_parquet(args)), flush=True)
         return 0
     n = 1 << args.log2_keys
     s, S, k = args.words_per_block, args.word_bits, args.k
@@ -1188,6 +1291,10 @@ def main() -> int:
         log("[bench] batched leg: 4096 filters, graph launch vs one launch per filter")
         result["batched"] = batched_summary(run_batched(argparse.Namespace(
             **{**vars(args), "steps": 5, "warmup": 1})))
+        torch.cuda.empty_cache()
+    if not args.no_parquet:
+        log("[bench] parquet leg: the format's largest filter, and row-group pruning")
+        result["parquet"] = run_parquet(argparse.Namespace(**{**vars(args), "steps": 5}))
         torch.cuda.empty_cache()
 
     if not args.no_cpu_baseline:
