@@ -952,6 +952,7 @@ def run_parquet(args) -> dict:
     torch.cuda.synchronize()
     build_ms = median_ms(build.launch, before=lambda: [g.clear() for g in filters])
     graph_ms = median_ms(prune.launch)
+    direct_ms = median_ms(prune.launch_direct)
     per_filter_ms = median_ms(prune_p.launch_per_filter)
     hits = out_g.view(rgs, lits).any(dim=1)
     res = {
@@ -964,7 +965,8 @@ def run_parquet(args) -> dict:
         "pruning": {
             "row_groups": rgs, "values_per_row_group": per_rg, "literals_per_row_group": lits,
             "build_gkeys_s": round(rgs * per_rg / (build_ms * 1e-3) / 1e9, 3),
-            "graph_us": round(graph_ms * 1e3, 2), "per_filter_us": round(per_filter_ms * 1e3, 2),
+            "graph_us": round(graph_ms * 1e3, 2), "direct_us": round(direct_ms * 1e3, 2),
+            "per_filter_us": round(per_filter_ms * 1e3, 2),
             "speedup_vs_per_filter": round(per_filter_ms / graph_ms, 2),
             "row_groups_per_s": round(rgs / (graph_ms * 1e-3), 1),
             "row_groups_kept": int(hits.sum().item()),

@@ -119,7 +119,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   PartLayout L{};
   if (!part_geometry(chunks, shift, n, a, L)) return BF_OK;
   PartKernels k = part_kernels(f0);
-  if (nfilters > 1) k.scatter1 = k.scatter1_multi;  // the first pass walks a table of filters
+  k.scatter1 = k.scatter1_multi;  // the first pass takes its key ranges from the work list
   if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_OK;
   // Per-bucket capacities from each chunk's expected load: filter i's keys
   // spread uniformly over its blocks (a chunk holding part of the filter
@@ -151,25 +151,27 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   L.off_buf2 = (8 * off1[a.f1] + 255) & ~255ull;
   L.off_fill = (L.off_buf2 + 8 * off2[chunks] + 255) & ~255ull;
   L.total = (L.off_fill + 8 * L.nfill + 255) & ~255ull;
-  // tables after the buffers: filters, chunk owners, first filter per
-  // first-pass workgroup
+  // tables after the buffers: filters, chunk owners, the first pass's work
+  // items (key ranges of at most range1 keys within one dense filter; the
+  // keys of direct filters are not read)
   std::vector<uint32_t> owner(chunks);
   for (uint32_t i = 0; i < nfilters; ++i) {
     const uint64_t c_end = i + 1 < nfilters ? pf[i + 1].chunk_base : chunks;
     std::fill(owner.begin() + static_cast<std::ptrdiff_t>(pf[i].chunk_base),
               owner.begin() + static_cast<std::ptrdiff_t>(c_end), i);
   }
-  const uint32_t g1 = part_grid1(a).x;
-  std::vector<uint32_t> first(g1);
-  for (uint32_t g = 0; g < g1; ++g) {
-    const uint64_t begin = static_cast<uint64_t>(g) * a.range1;
-    uint32_t lo = 0, hi = nfilters - 1;  // first filter with key_end > begin
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (pf[mid].key_end > begin) hi = mid; else lo = mid + 1;
-    }
-    first[g] = lo;
+  std::vector<PartRange> work1;
+  for (uint32_t i = 0; i < nfilters; ++i) {
+    if (pf[i].direct) continue;
+    for (uint64_t s = pf[i].key_begin; s < pf[i].key_end; s += a.range1)
+      work1.push_back(PartRange{s, std::min(s + a.range1, pf[i].key_end), i, 0});
   }
+  if (work1.empty() || work1.size() > 0x7fffffffull) return BF_OK;
+  // longest first: workgroups are dispatched in index order as CUs free up,
+  // so the short items fill the gaps at the end
+  std::stable_sort(work1.begin(), work1.end(), [](const PartRange& x, const PartRange& y) {
+    return x.end - x.begin > y.end - y.begin;
+  });
   const uint64_t off_pf = L.total;
   const uint64_t off_owner = (off_pf + pf.size() * sizeof(PartFilter) + 255) & ~255ull;
   const uint64_t off_first = (off_owner + owner.size() * 4 + 255) & ~255ull;
@@ -188,7 +190,7 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
     for (uint64_t i = 0; i < ns; ++i)
       work3.push_back(PartWork{static_cast<uint32_t>(c), static_cast<uint16_t>(i), static_cast<uint16_t>(ns)});
   }
-  const uint64_t off_ext1 = (off_first + first.size() * 4 + 255) & ~255ull;
+  const uint64_t off_ext1 = (off_first + work1.size() * sizeof(PartRange) + 255) & ~255ull;
   const uint64_t off_ext2 = (off_ext1 + off1.size() * 8 + 255) & ~255ull;
   const uint64_t off_w2 = (off_ext2 + off2.size() * 8 + 255) & ~255ull;
   const uint64_t off_w3 = (off_w2 + work2.size() * sizeof(PartWork) + 255) & ~255ull;
@@ -204,8 +206,8 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
           hipSuccess ||
       hipMemcpy(base + off_owner, owner.data(), owner.size() * 4, hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(base + off_first, first.data(), first.size() * 4, hipMemcpyHostToDevice) !=
-          hipSuccess ||
+      hipMemcpy(base + off_first, work1.data(), work1.size() * sizeof(PartRange),
+                hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(base + off_ext1, off1.data(), off1.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(base + off_ext2, off2.data(), off2.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
       hipMemcpy(base + off_w2, work2.data(), work2.size() * sizeof(PartWork), hipMemcpyHostToDevice) !=
@@ -227,7 +229,8 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   a.nb_hi_mask = pf[0].nb_hi_mask;
   a.filters = reinterpret_cast<const PartFilter*>(base + off_pf);
   a.chunk_owner = reinterpret_cast<const uint32_t*>(base + off_owner);
-  a.wg_first = reinterpret_cast<const uint32_t*>(base + off_first);
+  a.work1 = reinterpret_cast<const PartRange*>(base + off_first);
+  a.nwork1 = static_cast<uint32_t>(work1.size());
   a.nfilters = nfilters;
   a.k = f0->k;
   a.keys = d_keys + h_offsets[0];

@@ -162,7 +162,10 @@ bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels&
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
-dim3 part_grid1(const PartArgs& a) { return dim3(static_cast<uint32_t>((a.n + a.range1 - 1) / a.range1)); }
+dim3 part_grid1(const PartArgs& a) {
+  if (a.work1) return dim3(a.nwork1);
+  return dim3(static_cast<uint32_t>((a.n + a.range1 - 1) / a.range1));
+}
 dim3 part_grid2(const PartArgs& a) { return dim3(a.work2 ? a.nwork2 : a.f1 * a.q); }
 dim3 part_grid3(const PartArgs& a) {
   const uint64_t items = a.work3 ? a.nwork3 : a.chunks * std::max<uint32_t>(a.apply_split, 1);

@@ -94,7 +94,8 @@ struct PartArgs {
   // ... or a table of filters (nfilters > 1) sharing one layout and k
   const PartFilter* filters;
   const uint32_t* chunk_owner;  // global chunk -> filter
-  const uint32_t* wg_first;     // first filter of each first-pass workgroup's keys
+  const struct PartRange* work1;  // first-pass workgroup -> its keys (one filter's)
+  uint32_t nwork1;
   uint32_t nfilters;
   uint32_t k;
   uint32_t chunk_shift;  // log2(blocks per chunk)
@@ -135,6 +136,15 @@ struct PartArgs {
   // once by the slice's owner
   uint32_t g1;           // pass-1 workgroups
   uint64_t cs1;
+};
+
+// The keys [begin, end) of filter `filter`: one first-pass workgroup of a
+// multi-filter plan (at most range1 keys, never more than one filter's).
+struct PartRange {
+  uint64_t begin;
+  uint64_t end;
+  uint32_t filter;
+  uint32_t reserved;
 };
 
 // One unit of work: slice `split` of `nsplit` of bucket `bucket`.
@@ -464,33 +474,31 @@ struct Pass1Dest {
   }
 };
 
-// First pass: hash keys and group the records by high digit.  MULTI: keys
-// of a table of filters (each thread walks a cursor over the filters, its
-// key positions only increasing, and keeps the current filter's fields in
-// registers).  The one-filter loop is a separate copy: the cursor's loads,
-// merged into the key loop, would make the compiler wait for every
-// outstanding load (the prefetched keys included) before hashing.
+// First pass: hash keys and group the records by high digit.  MULTI: the
+// workgroup's keys are one work item of a multi-filter plan, a key range of
+// one filter, whose fields are read once before the key loop (per-key
+// lookups of the filter inside the loop would make the compiler wait for
+// every outstanding load, the prefetched keys included, before hashing).
 template <typename W, int S_WORDS, int K, int Z, bool MULTI>
 __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMaxDigits>& l) {
   constexpr int kPer1 = kPartStep / kScatter1Threads;
   const BlockRule<W, S_WORDS, K, Z> rule;
   const Pass1Dest<kMaxDigits, kScatter1Threads> dst{a, l};
   const uint32_t shift = a.chunk_shift + a.low_bits;
-  const uint64_t begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
-  const uint64_t end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
-  uint32_t cur = 0;
-  uint64_t cur_end = ~0ull, cur_hinit = a.hash_init, cur_base = 0;
-  uint32_t cur_lo = a.nb_lo, cur_hi = a.nb_hi_mask;
-  bool cur_direct = false;
+  uint64_t begin, end, hinit = a.hash_init, base = 0;
+  uint32_t nb_lo = a.nb_lo, nb_hi = a.nb_hi_mask;
   if constexpr (MULTI) {
-    cur = a.wg_first[blockIdx.x];
-    const PartFilter& f = a.filters[cur];
-    cur_end = f.key_end;
-    cur_hinit = f.hash_init;
-    cur_lo = f.nb_lo;
-    cur_hi = f.nb_hi_mask;
-    cur_base = f.block_base;
-    cur_direct = f.direct != 0;
+    const PartRange w = a.work1[blockIdx.x];
+    const PartFilter& f = a.filters[w.filter];
+    begin = w.begin;
+    end = w.end;
+    hinit = f.hash_init;
+    nb_lo = f.nb_lo;
+    nb_hi = f.nb_hi_mask;
+    base = f.block_base;
+  } else {
+    begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
+    end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
   }
   // The keys of the next step are loaded while this step hashes and sorts
   // (workgroup barriers do not wait for global loads), so their latency is
@@ -513,30 +521,15 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     if (s + kPartStep < end) load_keys(s + kPartStep);
     uint64_t r[kPer1];
     uint32_t dg[kPer1];
-    bool take[kPer1];
 #pragma unroll
     for (int j = 0; j < kPer1; ++j) {
-      if constexpr (MULTI) {
-        const uint64_t i = s + threadIdx.x + j * kScatter1Threads;
-        if (i >= cur_end) {  // moved past the current filter's keys
-          while (cur + 1 < a.nfilters && a.filters[cur].key_end <= i) ++cur;
-          const PartFilter& f = a.filters[cur];
-          cur_end = cur + 1 < a.nfilters ? f.key_end : ~0ull;
-          cur_hinit = f.hash_init;
-          cur_lo = f.nb_lo;
-          cur_hi = f.nb_hi_mask;
-          cur_base = f.block_base;
-          cur_direct = f.direct != 0;
-        }
-      }
-      const uint64_t h = xxh64_u64(key[j], cur_hinit);
-      const uint32_t blk = static_cast<uint32_t>(cur_base + block_of(h, cur_lo, cur_hi));
+      const uint64_t h = xxh64_u64(key[j], hinit);
+      const uint32_t blk = static_cast<uint32_t>(base + block_of(h, nb_lo, nb_hi));
       r[j] = (static_cast<uint64_t>(blk) << 32) | static_cast<uint32_t>(h);
       dg[j] = blk >> shift;
-      take[j] = threadIdx.x + j * kScatter1Threads < valid && !cur_direct;
     }
-    scatter_step_masked<kScatter1Threads>(
-        r, dg, [&take](int j) { return take[j]; }, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
+    scatter_step<kScatter1Threads>(
+        r, dg, valid, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
         a.buf1,
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
@@ -549,9 +542,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
   dst.publish();
 }
 
-// MULTI: the kernel of multi-filter plans.  The two loops are separate
-// kernels so that each gets its own register allocation (together they
-// needed more than the 128 VGPRs a 1024-thread workgroup allows, and spilled).
+// MULTI: the kernel of multi-filter plans (one work item per workgroup).
 template <typename W, int S_WORDS, int K, int Z = 0, bool MULTI = false>
 __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits> l;
