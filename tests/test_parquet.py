@@ -196,3 +196,22 @@ def test_library_rejects_bad_parquet_sizes_without_gpu():
         assert st == bf.BF_EINVAL
         st, _ = bf.bf_create_parquet_in(256, nb)
         assert st == bf.BF_EINVAL
+
+
+def test_header_parser_survives_arbitrary_bytes():
+    """Random and mutated headers: every call returns a status (no crash, no
+    hang), and an OK parse stays inside the bytes it was given."""
+    bf = _bf()
+    rng = np.random.default_rng(12)
+    st, good = bf.bf_parquet_header(1 << 20)
+    cases = [bytes(rng.integers(0, 256, size=int(n), dtype=np.uint8)) for n in rng.integers(0, 64, size=2000)]
+    for _ in range(2000):
+        m = bytearray(good + bytes(rng.integers(0, 256, size=8, dtype=np.uint8)))
+        for _ in range(int(rng.integers(1, 4))):
+            m[int(rng.integers(0, len(m)))] = int(rng.integers(0, 256))
+        cases.append(bytes(m))
+    for blob in cases:
+        st, nb, hl = bf.bf_parquet_parse_header(blob)
+        assert st in (bf.BF_OK, bf.BF_EINVAL, bf.BF_EUNSUPPORTED)
+        if st == bf.BF_OK:
+            assert 0 < hl <= len(blob) and nb > 0 and nb % 32 == 0
