@@ -91,7 +91,7 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *   strategy        add only: BF_STRATEGY_*.  The partitioned strategy
  *                   radix-partitions the keys by 64 KiB filter chunk and
  *                   updates each chunk in LDS, so a bulk add performs no
- *                   global atomics; it takes a workspace of 17-21 bytes per key
+ *                   global atomics; it takes a workspace of 14-22 bytes per key
  *                   from a per-device stream-ordered memory pool and returns
  *                   it at its end on the same stream (no device
  *                   synchronization; the pool keeps its peak size reserved
@@ -210,7 +210,7 @@ bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
  * add mapping: BF_STRATEGY_DIRECT or BF_STRATEGY_PARTITIONED, the automatic
  * choice resolved by the measured crossover (partitioned from about 1.5 M
  * keys + filter bytes / 80; for the classic layout n counts k records per
- * key).  For callers that plan workspace memory (17-21 bytes per key for a
+ * key).  For callers that plan workspace memory (14-22 bytes per key for a
  * partitioned add).  Host only: enqueues nothing and touches no device.
  * BF_EINVAL if f or out is NULL. */
 bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
@@ -235,10 +235,10 @@ bf_status bf_tuned_mapping(int op, uint64_t num_blocks, uint32_t words_per_block
  * library's code on the first call there and kept until the process ends.
  * An add the automatic rule builds directly (one atomic OR group per key)
  * needs no workspace and is bf_add itself.  A partitioned add must fit one
- * pass of the array (at most 2^28 records; the workspace is about 17-25
- * bytes per key plus about 650 bytes per 64 KiB chunk of filter, so up to
- * about 14 M keys into filters of 64 MiB or less and 10 M into a 1 GiB
- * filter): larger adds give BF_ESCRATCH with nothing enqueued.  Calls on one device
+ * pass of the array (at most 2^28 records; the workspace is about 14-22
+ * bytes per key, the most for few keys into a large filter, so up to about
+ * 16 M keys into filters of 64 MiB or less and 12 M into a 1 GiB filter):
+ * larger adds give BF_ESCRATCH with nothing enqueued.  Calls on one device
  * share the array, which keeps the last call's contents (the kernels clear
  * the counters they need): outside graph capture the library orders them
  * with one event per device, so they never overlap; calls captured into

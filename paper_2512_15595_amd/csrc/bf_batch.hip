@@ -148,8 +148,8 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   }
   // buffers sized by the extents (replacing the uniform layout)
   L.off_buf1 = 0;
-  L.off_buf2 = (8 * off1[a.f1] + 255) & ~255ull;
-  L.off_fill = (L.off_buf2 + 8 * off2[chunks] + 255) & ~255ull;
+  uint64_t off = (8 * off1[a.f1] + 255) & ~255ull;
+  part_buf2(L, off, off2[chunks]);
   L.total = (L.off_fill + 8 * L.nfill + 255) & ~255ull;
   // tables after the buffers: filters, chunk owners, the first pass's work
   // items (key ranges of at most range1 keys within one dense filter; the

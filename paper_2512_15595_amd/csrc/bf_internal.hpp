@@ -58,7 +58,7 @@ namespace bfhip {
 // Partitioned construction (bf_partition.hip).
 struct PartArgs;
 struct PartLayout {
-  uint64_t off_buf1, off_buf2, off_fill, nfill1, nfill, total;
+  uint64_t off_buf1, off_buf2, off_blk2, off_fill, nfill1, nfill, total;
 };
 struct PartKernels {
   const void* scatter1;
@@ -84,6 +84,7 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
 // count keys.
 void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key);
 void part_bind(PartArgs& a, const PartLayout& L, void* base);
+void part_buf2(PartLayout& L, uint64_t& off, uint64_t slots);
 PartKernels part_kernels(const bf_filter* f);
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k, hipStream_t stream);
 dim3 part_grid1(const PartArgs& a);

@@ -49,6 +49,16 @@ uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits) {
   return shift;
 }
 
+// The chunk buckets' two arrays from byte offset `off` (advanced past them):
+// `slots` lo32 words, then `slots` 16-bit blocks.
+void part_buf2(PartLayout& L, uint64_t& off, uint64_t slots) {
+  L.off_buf2 = off;
+  off = align256(off + 4 * slots);
+  L.off_blk2 = off;
+  off = align256(off + 2 * slots);
+  L.off_fill = off;
+}
+
 bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L) {
   a.chunk_shift = chunk_shift;
   a.chunks = chunks;
@@ -82,9 +92,7 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
   uint64_t off = 0;
   L.off_buf1 = off;
   off = align256(off + 8ull * a.f1 * a.cap1);
-  L.off_buf2 = off;
-  off = align256(off + 8ull * chunks * a.cap2);
-  L.off_fill = off;
+  part_buf2(L, off, chunks * a.cap2);
   L.nfill1 = a.f1;
   L.nfill = a.f1 + chunks;
   off = align256(off + 8ull * L.nfill);
@@ -104,9 +112,7 @@ void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key) {
   uint64_t off = 0;
   L.off_buf1 = off;
   off = align256(off + 8ull * a.f1 * a.g1 * a.cs1);
-  L.off_buf2 = off;
-  off = align256(off + 8ull * a.chunks * a.cap2);
-  L.off_fill = off;
+  part_buf2(L, off, a.chunks * a.cap2);
   L.nfill1 = static_cast<uint64_t>(a.f1) * a.g1;
   L.nfill = L.nfill1 + a.chunks;
   off = align256(off + 8ull * L.nfill);
@@ -116,7 +122,8 @@ void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key) {
 void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
   uint8_t* base = static_cast<uint8_t*>(base_ptr);
   a.buf1 = reinterpret_cast<uint64_t*>(base + L.off_buf1);
-  a.buf2 = reinterpret_cast<uint64_t*>(base + L.off_buf2);
+  a.buf2 = reinterpret_cast<uint32_t*>(base + L.off_buf2);
+  a.blk2 = reinterpret_cast<uint16_t*>(base + L.off_blk2);
   a.fill1 = reinterpret_cast<unsigned long long*>(base + L.off_fill);
   a.fill2 = a.fill1 + L.nfill1;
 }

@@ -15,8 +15,9 @@
 // reason, Sec. V-A), into fixed-capacity buckets:
 //   scatter1  keys -> hashed records (block << 32 | lo32) into high-digit
 //             buckets;                                        [8 B in, 8 out]
-//   scatter2  records -> chunk buckets;                       [8 in, 8 out]
-//   apply     per chunk: LDS load, LDS atomic OR, store;      [8 in + chunk]
+//   scatter2  records -> chunk buckets as (lo32, block within the chunk)
+//             pairs in two arrays;                            [8 in, 6 out]
+//   apply     per chunk: LDS load, LDS atomic OR, store;      [6 in + chunk]
 // Each scatter step counting-sorts kPartStep records in LDS, so a digit
 // leaves the step as one contiguous run.  Where the run goes:
 //   chunk buckets, and the high-digit buckets of multi-filter plans (whose
@@ -110,7 +111,8 @@ struct PartArgs {
   uint64_t* buf1;        // f1 buckets of cap1 records (or per off1)
   unsigned long long* fill1;
   uint64_t cap1;
-  uint64_t* buf2;        // chunk buckets of cap2 records (or per off2)
+  uint32_t* buf2;        // chunk buckets of cap2 records (or per off2): lo32 ...
+  uint16_t* blk2;        // ... and block within the chunk (a chunk has at most 2^14 blocks)
   unsigned long long* fill2;
   uint64_t cap2;
   // optional per-bucket extents (multi-filter plans, whose chunks expect
@@ -347,16 +349,16 @@ __device__ __forceinline__ void slice_walk(const uint32_t* pre, uint32_t& i0, ui
 // over the workgroup.
 // For every digit d with records, claim(d, cnt, gbase[d], room[d]) reserves
 // a run of cnt records in digit d's destination: the run starts at record
-// gbase[d] of buf and its first room[d] <= cnt records fit; the others go
-// to `overflow`.  The per-digit figures live in LDS so that the store loop
+// gbase[d] of the destination, where store(i, v) puts record v at index i,
+// and its first room[d] <= cnt records fit; the others go to `overflow`.  The per-digit figures live in LDS so that the store loop
 // touches nothing but LDS and the stores themselves (with a global load or
 // an atomic anywhere in it, the compiler waits for every outstanding memory
 // operation before each store).
-template <int THREADS, typename ValidOf, typename DigitOf, typename Claim, typename Overflow>
+template <int THREADS, typename ValidOf, typename Store, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step_masked(
     const uint64_t (&r)[kPartStep / THREADS], const uint32_t (&dg)[kPartStep / THREADS], ValidOf valid_of,
     uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start, uint64_t* gbase, uint32_t* room,
-    uint32_t* ntotal, uint64_t* buf, DigitOf digit_of, Claim claim, Overflow overflow) {
+    uint32_t* ntotal, Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
   constexpr int PER = kPartStep / THREADS;
   uint32_t rank[PER];
 #pragma unroll
@@ -402,7 +404,7 @@ __device__ __forceinline__ void scatter_step_masked(
       const uint32_t d = digit_of(v);
       const uint32_t q = p - start[d];
       if (q < room[d])
-        buf[gbase[d] + q] = v;
+        store(gbase[d] + q, v);
       else
         spill = true;
     }
@@ -420,15 +422,15 @@ __device__ __forceinline__ void scatter_step_masked(
 }
 
 // The common case: the first `valid` positions p = tid + j * THREADS.
-template <int THREADS, typename DigitOf, typename Claim, typename Overflow>
+template <int THREADS, typename Store, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartStep / THREADS],
                                              const uint32_t (&dg)[kPartStep / THREADS], uint32_t valid,
                                              uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start,
-                                             uint64_t* gbase, uint32_t* room, uint32_t* ntotal, uint64_t* buf,
+                                             uint64_t* gbase, uint32_t* room, uint32_t* ntotal, Store store,
                                              DigitOf digit_of, Claim claim, Overflow overflow) {
   scatter_step_masked<THREADS>(
       r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, ndigits, stage, cnt, start, gbase,
-      room, ntotal, buf, digit_of, claim, overflow);
+      room, ntotal, store, digit_of, claim, overflow);
 }
 
 // A run of c records at offset b of a destination of cap records: how many fit.
@@ -530,7 +532,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     }
     scatter_step<kScatter1Threads>(
         r, dg, valid, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
-        a.buf1,
+        [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
         [&](uint64_t v) {
@@ -601,7 +603,8 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
     }
     scatter_step_masked<kClassicThreads>(
         r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room,
-        &l.total, a.buf1, [shift](uint64_t v) { return rec_block(v) >> shift; },
+        &l.total, [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
+        [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
         [&](uint64_t v) {
           rule.add_global(static_cast<uint32_t*>(a.words), rec_block(v), rec_lo(v), 0);
@@ -656,6 +659,7 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
     src = a.buf1 + bucket1_base(a, d1);
   }
   const uint32_t cshift = a.chunk_shift, mask = a.f2 - 1, f2 = a.f2;
+  const uint32_t local_mask = (1u << a.chunk_shift) - 1;
   const uint64_t cbase = static_cast<uint64_t>(d1) * f2;  // global chunk of digit 0
   uint32_t i0 = 0;  // sliced mode: slice of the previous step's last position
   for (uint64_t s = begin; s < end; s += kPartStep) {
@@ -674,7 +678,11 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
       dg[j] = (rec_block(r[j]) >> cshift) & mask;
     }
     scatter_step<kScatter2Threads>(
-        r, dg, valid, f2, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total, a.buf2,
+        r, dg, valid, f2, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
+        [&a, local_mask](uint64_t i, uint64_t v) {
+          a.buf2[i] = rec_lo(v);
+          a.blk2[i] = static_cast<uint16_t>(rec_block(v) & local_mask);
+        },
         [cshift, mask](uint64_t v) { return (rec_block(v) >> cshift) & mask; },
         [&](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) {
           const uint64_t b = atomicAdd(&a.fill2[cbase + d], static_cast<unsigned long long>(c));
@@ -700,7 +708,6 @@ __global__ __launch_bounds__(kApplyThreads, 8) void part_apply_kernel(PartArgs a
   u32x4* lvec = reinterpret_cast<u32x4*>(lds_raw);
   const BlockRule<W, S_WORDS, K, Z> rule;
   const uint32_t blocks_per_chunk = 1u << a.chunk_shift;
-  const uint32_t local_mask = blocks_per_chunk - 1;
   constexpr int kU = 4;
   const uint32_t split = a.apply_split > 1 ? a.apply_split : 1;
   const uint64_t nitems = a.work3 ? a.nwork3 : a.chunks * split;
@@ -722,7 +729,8 @@ __global__ __launch_bounds__(kApplyThreads, 8) void part_apply_kernel(PartArgs a
     const uint64_t rbegin = filled * si / ns;
     const uint64_t count = filled * (si + 1) / ns - rbegin;
     if (count == 0) continue;  // untouched: no traffic at all
-    const uint64_t* recs = a.buf2 + bucket2_base(a, c) + rbegin;
+    const uint32_t* los = a.buf2 + bucket2_base(a, c) + rbegin;
+    const uint16_t* blks = a.blk2 + bucket2_base(a, c) + rbegin;
     W* words = static_cast<W*>(a.words);
     uint64_t num_blocks = a.num_blocks, local_chunk = c;
     if (a.nfilters > 1) {
@@ -768,17 +776,16 @@ __global__ __launch_bounds__(kApplyThreads, 8) void part_apply_kernel(PartArgs a
     }
     __syncthreads();
     for (uint64_t i = threadIdx.x; i < count; i += kU * kApplyThreads) {
-      uint64_t r[kU];
+      uint32_t lo[kU], lb[kU];
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const uint64_t j = i + static_cast<uint64_t>(u) * kApplyThreads;
-        r[u] = j < count ? recs[j] : 0;
+        lo[u] = j < count ? los[j] : 0;
+        lb[u] = j < count ? blks[j] : 0;
       }
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        if (i + static_cast<uint64_t>(u) * kApplyThreads < count) {
-          rule.add_lds(lds, rec_block(r[u]) & local_mask, rec_lo(r[u]), a.k);
-        }
+        if (i + static_cast<uint64_t>(u) * kApplyThreads < count) rule.add_lds(lds, lb[u], lo[u], a.k);
       }
     }
     __syncthreads();

@@ -86,7 +86,7 @@ def test_noalloc_rejects_adds_beyond_the_array_and_enqueues_nothing():
     lib = _lib()
     f = bf.BloomFilter((1 << 30) // 32, 8, 32, 8, 7)          # 1 GiB
     f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
-    n = 12_000_000                                             # needs more than the array
+    n = 16_000_000                                             # needs more than the array
     d = torch.zeros(n, dtype=torch.int64, device="cuda")
     try:
         rc = lib.bf_add_noalloc(f.handle, d.data_ptr(), n, torch.cuda.current_stream().cuda_stream)
