@@ -350,15 +350,18 @@ __device__ __forceinline__ void slice_walk(const uint32_t* pre, uint32_t& i0, ui
 // For every digit d with records, claim(d, cnt, gbase[d], room[d]) reserves
 // a run of cnt records in digit d's destination: the run starts at record
 // gbase[d] of the destination, where store(i, v) puts record v at index i,
-// and its first room[d] <= cnt records fit; the others go to `overflow`.  The per-digit figures live in LDS so that the store loop
-// touches nothing but LDS and the stores themselves (with a global load or
-// an atomic anywhere in it, the compiler waits for every outstanding memory
-// operation before each store).
+// and its first room[d] <= cnt records fit; the thread that reads one of the
+// others in the store loop hands it to `overflow`.  The per-digit figures
+// live in LDS so that the store loop reads nothing else.
+// cnt holds this step's digit counts and is zero on entry; the step zeroes
+// cnt_next for the next one, so the counts need no reset of their own.  The
+// step has three workgroup barriers, and the time of a scatter pass is set
+// by them and by the LDS work between them more than by its HBM traffic.
 template <int THREADS, typename ValidOf, typename Store, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step_masked(
     const uint64_t (&r)[kPartStep / THREADS], const uint32_t (&dg)[kPartStep / THREADS], ValidOf valid_of,
-    uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start, uint64_t* gbase, uint32_t* room,
-    uint32_t* ntotal, Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
+    uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* cnt_next, uint32_t* start, uint64_t* gbase,
+    uint32_t* room, uint32_t* ntotal, Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
   constexpr int PER = kPartStep / THREADS;
   uint32_t rank[PER];
 #pragma unroll
@@ -394,8 +397,8 @@ __device__ __forceinline__ void scatter_step_masked(
   for (int j = 0; j < PER; ++j) {
     if (valid_of(j)) stage[start[dg[j]] + rank[j]] = r[j];
   }
+  for (uint32_t d = threadIdx.x; d < ndigits; d += THREADS) cnt_next[d] = 0;
   __syncthreads();
-  bool spill = false;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {  // total <= kPartStep
     const uint32_t p = threadIdx.x + j * THREADS;
@@ -406,31 +409,21 @@ __device__ __forceinline__ void scatter_step_masked(
       if (q < room[d])
         store(gbase[d] + q, v);
       else
-        spill = true;
+        overflow(v);  // past its destination's capacity: applied directly
     }
   }
-  if (__syncthreads_or(spill)) {  // records past their capacity: applied directly
-    for (uint32_t p = threadIdx.x; p < total; p += THREADS) {
-      const uint64_t v = stage[p];
-      const uint32_t d = digit_of(v);
-      if (p - start[d] >= room[d]) overflow(v);
-    }
-    __syncthreads();
-  }
-  for (uint32_t d = threadIdx.x; d < ndigits; d += THREADS) cnt[d] = 0;
-  __syncthreads();
 }
 
 // The common case: the first `valid` positions p = tid + j * THREADS.
 template <int THREADS, typename Store, typename DigitOf, typename Claim, typename Overflow>
 __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartStep / THREADS],
                                              const uint32_t (&dg)[kPartStep / THREADS], uint32_t valid,
-                                             uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* start,
-                                             uint64_t* gbase, uint32_t* room, uint32_t* ntotal, Store store,
-                                             DigitOf digit_of, Claim claim, Overflow overflow) {
+                                             uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* cnt_next,
+                                             uint32_t* start, uint64_t* gbase, uint32_t* room, uint32_t* ntotal,
+                                             Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
   scatter_step_masked<THREADS>(
-      r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, ndigits, stage, cnt, start, gbase,
-      room, ntotal, store, digit_of, claim, overflow);
+      r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, ndigits, stage, cnt, cnt_next, start,
+      gbase, room, ntotal, store, digit_of, claim, overflow);
 }
 
 // A run of c records at offset b of a destination of cap records: how many fit.
@@ -443,7 +436,7 @@ template <int D>
 struct ScatterLds {
   uint64_t stage[kPartStep];
   uint64_t gbase[D];
-  uint32_t cnt[D];
+  uint32_t cnt[2][D];  // digit counts of even and odd steps
   uint32_t start[D];
   uint32_t room[D];
   uint32_t fill[D];  // sliced mode: records written to this workgroup's slice
@@ -515,7 +508,8 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     }
   };
   if (begin < end) load_keys(begin);
-  for (uint64_t s = begin; s < end; s += kPartStep) {
+  uint32_t par = 0;  // which digit-count buffer this step uses
+  for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
     uint64_t key[kPer1];
 #pragma unroll
@@ -531,7 +525,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
       dg[j] = blk >> shift;
     }
     scatter_step<kScatter1Threads>(
-        r, dg, valid, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
+        r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
         [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
@@ -549,7 +543,8 @@ template <typename W, int S_WORDS, int K, int Z = 0, bool MULTI = false>
 __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits> l;
   for (uint32_t d = threadIdx.x; d < a.f1; d += kScatter1Threads) {
-    l.cnt[d] = 0;
+    l.cnt[0][d] = 0;
+    l.cnt[1][d] = 0;
     l.fill[d] = 0;
   }
   __syncthreads();
@@ -567,7 +562,8 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
   static_assert(kKeys >= 1, "at most kPer positions per key");
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits> l;
   for (uint32_t d = threadIdx.x; d < a.f1; d += kClassicThreads) {
-    l.cnt[d] = 0;
+    l.cnt[0][d] = 0;
+    l.cnt[1][d] = 0;
     l.fill[d] = 0;
   }
   __syncthreads();
@@ -577,7 +573,8 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
   constexpr uint64_t kStepKeys = static_cast<uint64_t>(kClassicThreads) * kKeys;
   const uint64_t begin = static_cast<uint64_t>(blockIdx.x) * a.range1;
   const uint64_t end = begin + a.range1 < a.n ? begin + a.range1 : a.n;
-  for (uint64_t s = begin; s < end; s += kStepKeys) {
+  uint32_t par = 0;  // which digit-count buffer this step uses
+  for (uint64_t s = begin; s < end; s += kStepKeys, par ^= 1u) {
     const uint32_t vkeys = static_cast<uint32_t>(end - s < kStepKeys ? end - s : kStepKeys);
     bool ok[kKeys];
     uint64_t r[kPer];
@@ -602,7 +599,8 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
       dg[j] = 0;
     }
     scatter_step_masked<kClassicThreads>(
-        r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, a.f1, l.stage, l.cnt, l.start, l.gbase, l.room,
+        r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1],
+        l.start, l.gbase, l.room,
         &l.total, [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
@@ -622,7 +620,8 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits2> l;
   __shared__ uint32_t pre[kMaxSlices + 1];
   for (uint32_t d = threadIdx.x; d < a.f2; d += kScatter2Threads) {
-    l.cnt[d] = 0;
+    l.cnt[0][d] = 0;
+    l.cnt[1][d] = 0;
     l.fill[d] = 0;
   }
   __syncthreads();
@@ -662,7 +661,8 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
   const uint32_t local_mask = (1u << a.chunk_shift) - 1;
   const uint64_t cbase = static_cast<uint64_t>(d1) * f2;  // global chunk of digit 0
   uint32_t i0 = 0;  // sliced mode: slice of the previous step's last position
-  for (uint64_t s = begin; s < end; s += kPartStep) {
+  uint32_t par = 0;  // which digit-count buffer this step uses
+  for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
     uint64_t r[kPer2];
     uint32_t dg[kPer2];
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
       dg[j] = (rec_block(r[j]) >> cshift) & mask;
     }
     scatter_step<kScatter2Threads>(
-        r, dg, valid, f2, l.stage, l.cnt, l.start, l.gbase, l.room, &l.total,
+        r, dg, valid, f2, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
         [&a, local_mask](uint64_t i, uint64_t v) {
           a.buf2[i] = rec_lo(v);
           a.blk2[i] = static_cast<uint16_t>(rec_block(v) & local_mask);
