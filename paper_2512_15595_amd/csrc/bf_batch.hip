@@ -148,7 +148,9 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   }
   // buffers sized by the extents (replacing the uniform layout)
   L.off_buf1 = 0;
-  uint64_t off = (8 * off1[a.f1] + 255) & ~255ull;
+  a.spare1 = off1[a.f1];
+  a.spare2 = off2[chunks];
+  uint64_t off = (8 * (off1[a.f1] + kSpareSlots) + 255) & ~255ull;
   part_buf2(L, off, off2[chunks]);
   L.total = (L.off_fill + 8 * L.nfill + 255) & ~255ull;
   // tables after the buffers: filters, chunk owners, the first pass's work

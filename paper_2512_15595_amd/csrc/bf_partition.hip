@@ -50,12 +50,12 @@ uint32_t part_chunk_shift(uint32_t words_per_block, uint32_t word_bits) {
 }
 
 // The chunk buckets' two arrays from byte offset `off` (advanced past them):
-// `slots` lo32 words, then `slots` 16-bit blocks.
+// `slots` lo32 words and kSpareSlots spare ones, then as many 16-bit blocks.
 void part_buf2(PartLayout& L, uint64_t& off, uint64_t slots) {
   L.off_buf2 = off;
-  off = align256(off + 4 * slots);
+  off = align256(off + 4 * (slots + kSpareSlots));
   L.off_blk2 = off;
-  off = align256(off + 2 * slots);
+  off = align256(off + 2 * (slots + kSpareSlots));
   L.off_fill = off;
 }
 
@@ -91,8 +91,10 @@ bool part_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& 
       std::min<uint64_t>(split_fill, n / chunks / 8192), 1, 1024));
   uint64_t off = 0;
   L.off_buf1 = off;
-  off = align256(off + 8ull * a.f1 * a.cap1);
-  part_buf2(L, off, chunks * a.cap2);
+  a.spare1 = static_cast<uint64_t>(a.f1) * a.cap1;
+  off = align256(off + 8ull * (a.spare1 + kSpareSlots));
+  a.spare2 = chunks * a.cap2;
+  part_buf2(L, off, a.spare2);
   L.nfill1 = a.f1;
   L.nfill = a.f1 + chunks;
   off = align256(off + 8ull * L.nfill);
@@ -111,8 +113,10 @@ void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key) {
   a.cs1 = capacity(static_cast<double>(a.range1 * records_per_key) / a.f1, 16, 16);
   uint64_t off = 0;
   L.off_buf1 = off;
-  off = align256(off + 8ull * a.f1 * a.g1 * a.cs1);
-  part_buf2(L, off, a.chunks * a.cap2);
+  a.spare1 = static_cast<uint64_t>(a.f1) * a.g1 * a.cs1;
+  off = align256(off + 8ull * (a.spare1 + kSpareSlots));
+  a.spare2 = a.chunks * a.cap2;
+  part_buf2(L, off, a.spare2);
   L.nfill1 = static_cast<uint64_t>(a.f1) * a.g1;
   L.nfill = L.nfill1 + a.chunks;
   off = align256(off + 8ull * L.nfill);

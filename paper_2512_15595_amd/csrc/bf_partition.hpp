@@ -59,6 +59,7 @@ constexpr int kClassicThreads = 512;
 constexpr int kZeroThreads = 256;
 constexpr int kApplyThreads = 1024;                 // apply: 16 waves share one chunk
 constexpr int kChunkBytes = 64 * 1024;              // LDS bytes owned per chunk
+constexpr int kSpareSlots = 64;                     // spare record slots per record array (one per lane)
 constexpr int kMaxDigits = 1024;                    // digit fan-out limit of the first pass
 constexpr int kMaxDigits2 = 512;                    // ... and of the second (chunks per high digit)
 constexpr int kMaxSlices = 1024;                    // slices one sliced-mode reader concatenates
@@ -138,6 +139,12 @@ struct PartArgs {
   // once by the slice's owner
   uint32_t g1;           // pass-1 workgroups
   uint64_t cs1;
+  // first of 64 spare record slots at the end of buf1 / of buf2 and blk2:
+  // a store loop writes every lane's record slot on every step, those of
+  // no record to a spare one, so that the number of stores per step is
+  // fixed (see scatter_step_masked)
+  uint64_t spare1;
+  uint64_t spare2;
 };
 
 // The keys [begin, end) of filter `filter`: one first-pass workgroup of a
@@ -354,14 +361,19 @@ __device__ __forceinline__ void slice_walk(const uint32_t* pre, uint32_t& i0, ui
 // others in the store loop hands it to `overflow`.  The per-digit figures
 // live in LDS so that the store loop reads nothing else.
 // cnt holds this step's digit counts and is zero on entry; the step zeroes
-// cnt_next for the next one, so the counts need no reset of their own.  The
-// step has three workgroup barriers, and the time of a scatter pass is set
-// by them and by the LDS work between them more than by its HBM traffic.
-template <int THREADS, typename ValidOf, typename Store, typename DigitOf, typename Claim, typename Overflow>
+// cnt_next for the next one, so the counts need no reset of their own.
+// after_claims() runs once the claims are done: a caller loads the next
+// step's records there.  Every lane stores PER records per step, the slots
+// of no record going to spare + lane, so the stores of a step are a fixed
+// number and a caller can wait for loads it issued before them with a
+// vmcnt that leaves the stores in flight.
+template <int THREADS, typename ValidOf, typename Store, typename DigitOf, typename Claim, typename Overflow,
+          typename AfterClaims>
 __device__ __forceinline__ void scatter_step_masked(
     const uint64_t (&r)[kPartStep / THREADS], const uint32_t (&dg)[kPartStep / THREADS], ValidOf valid_of,
     uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* cnt_next, uint32_t* start, uint64_t* gbase,
-    uint32_t* room, uint32_t* ntotal, Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
+    uint32_t* room, uint32_t* ntotal, uint64_t spare, Store store, DigitOf digit_of, Claim claim,
+    Overflow overflow, AfterClaims after_claims) {
   constexpr int PER = kPartStep / THREADS;
   uint32_t rank[PER];
 #pragma unroll
@@ -392,6 +404,7 @@ __device__ __forceinline__ void scatter_step_masked(
     if (threadIdx.x == 63) *ntotal = incl;
   }
   __syncthreads();
+  after_claims();
   const uint32_t total = *ntotal;
 #pragma unroll
   for (int j = 0; j < PER; ++j) {
@@ -399,32 +412,37 @@ __device__ __forceinline__ void scatter_step_masked(
   }
   for (uint32_t d = threadIdx.x; d < ndigits; d += THREADS) cnt_next[d] = 0;
   __syncthreads();
+  const uint64_t lane_spare = spare + (threadIdx.x & 63u);
 #pragma unroll
   for (int j = 0; j < PER; ++j) {  // total <= kPartStep
     const uint32_t p = threadIdx.x + j * THREADS;
-    if (p < total) {
-      const uint64_t v = stage[p];
-      const uint32_t d = digit_of(v);
-      const uint32_t q = p - start[d];
-      if (q < room[d])
-        store(gbase[d] + q, v);
-      else
-        overflow(v);  // past its destination's capacity: applied directly
-    }
+    const bool in = p < total;
+    const uint64_t v = stage[p];  // stale past total: not used then
+    const uint32_t d = in ? digit_of(v) : 0u;
+    const uint32_t q = p - start[d];
+    const bool fits = in && q < room[d];
+    if (in && !fits) overflow(v);  // past its destination's capacity: applied directly
+    store(fits ? gbase[d] + q : lane_spare, v);
   }
 }
 
 // The common case: the first `valid` positions p = tid + j * THREADS.
-template <int THREADS, typename Store, typename DigitOf, typename Claim, typename Overflow>
+template <int THREADS, typename Store, typename DigitOf, typename Claim, typename Overflow, typename AfterClaims>
 __device__ __forceinline__ void scatter_step(const uint64_t (&r)[kPartStep / THREADS],
                                              const uint32_t (&dg)[kPartStep / THREADS], uint32_t valid,
                                              uint32_t ndigits, uint64_t* stage, uint32_t* cnt, uint32_t* cnt_next,
                                              uint32_t* start, uint64_t* gbase, uint32_t* room, uint32_t* ntotal,
-                                             Store store, DigitOf digit_of, Claim claim, Overflow overflow) {
+                                             uint64_t spare, Store store, DigitOf digit_of, Claim claim,
+                                             Overflow overflow, AfterClaims after_claims) {
   scatter_step_masked<THREADS>(
       r, dg, [valid](int j) { return threadIdx.x + j * THREADS < valid; }, ndigits, stage, cnt, cnt_next, start,
-      gbase, room, ntotal, store, digit_of, claim, overflow);
+      gbase, room, ntotal, spare, store, digit_of, claim, overflow, after_claims);
 }
+
+// s_waitcnt operands (gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8) that wait until at most N vector memory operations
+// are outstanding and leave the other counters alone.
+constexpr int wait_vmcnt(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 // A run of c records at offset b of a destination of cap records: how many fit.
 __device__ __forceinline__ uint32_t run_room(uint64_t b, uint32_t c, uint64_t cap) {
@@ -508,8 +526,14 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
     }
   };
   if (begin < end) load_keys(begin);
+  // the first keys are waited for here, so that at the top of every step
+  // the outstanding operations are those of the previous step
+  __builtin_amdgcn_s_waitcnt(wait_vmcnt(0));
   uint32_t par = 0;  // which digit-count buffer this step uses
   for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
+    // this step's keys were loaded before the previous step's kPer1 record
+    // stores: wait for them only
+    __builtin_amdgcn_s_waitcnt(wait_vmcnt(kPer1));
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
     uint64_t key[kPer1];
 #pragma unroll
@@ -525,7 +549,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
       dg[j] = blk >> shift;
     }
     scatter_step<kScatter1Threads>(
-        r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
+        r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total, a.spare1,
         [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
@@ -533,7 +557,8 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
           uint32_t local;
           W* w = record_target<W>(a, rec_block(v), local);
           rule.add_global(w, local, rec_lo(v), a.k);
-        });
+        },
+        [] {});
   }
   dst.publish();
 }
@@ -600,13 +625,13 @@ __global__ __launch_bounds__(kClassicThreads) void part_scatter1_classic_kernel(
     }
     scatter_step_masked<kClassicThreads>(
         r, dg, [&](int j) { return j < kRecs && ok[j / K]; }, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1],
-        l.start, l.gbase, l.room,
-        &l.total, [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
+        l.start, l.gbase, l.room, &l.total, a.spare1, [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
         [shift](uint64_t v) { return rec_block(v) >> shift; },
         [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
         [&](uint64_t v) {
           rule.add_global(static_cast<uint32_t*>(a.words), rec_block(v), rec_lo(v), 0);
-        });
+        },
+        [] {});
   }
   dst.publish();
 }
@@ -660,25 +685,45 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
   const uint32_t cshift = a.chunk_shift, mask = a.f2 - 1, f2 = a.f2;
   const uint32_t local_mask = (1u << a.chunk_shift) - 1;
   const uint64_t cbase = static_cast<uint64_t>(d1) * f2;  // global chunk of digit 0
-  uint32_t i0 = 0;  // sliced mode: slice of the previous step's last position
-  uint32_t par = 0;  // which digit-count buffer this step uses
-  for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
-    const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
-    uint64_t r[kPer2];
-    uint32_t dg[kPer2];
+  uint32_t i0 = 0;  // sliced mode: slice of the last position loaded
+  // The records of the next step are loaded once this step's claims are
+  // done (a claim is a returning atomic, whose wait would take them too),
+  // while the step stages and stores its own.
+  uint64_t next[kPer2];
+  auto load_records = [&](uint64_t s0) {
+    const uint32_t v0 = static_cast<uint32_t>(end - s0 < kPartStep ? end - s0 : kPartStep);
     uint32_t delta[kPer2];
+#pragma unroll
+    for (int j = 0; j < kPer2; ++j) delta[j] = 0;
     if (sliced)
-      slice_walk(pre, i0, static_cast<uint32_t>(s), static_cast<uint32_t>(s) + valid - 1, kScatter2Threads,
+      slice_walk(pre, i0, static_cast<uint32_t>(s0), static_cast<uint32_t>(s0) + v0 - 1, kScatter2Threads,
                  static_cast<uint32_t>(a.cs1), delta);
 #pragma unroll
     for (int j = 0; j < kPer2; ++j) {
       const uint32_t p = threadIdx.x + j * kScatter2Threads;
-      r[j] = 0;
-      if (p < valid) r[j] = src[sliced ? static_cast<uint32_t>(s) + p + delta[j] : s + p];
+      next[j] = p < v0 ? src[sliced ? static_cast<uint32_t>(s0) + p + delta[j] : s0 + p] : 0;
+    }
+  };
+  if (begin < end) load_records(begin);
+  // the first records are waited for here, so that at the top of every
+  // step the outstanding operations are those of the previous step
+  __builtin_amdgcn_s_waitcnt(wait_vmcnt(0));
+  uint32_t par = 0;  // which digit-count buffer this step uses
+  for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
+    // this step's records were loaded before the previous step's stores
+    // (two per record: lo32 and block): wait for them only
+    __builtin_amdgcn_s_waitcnt(wait_vmcnt(2 * kPer2));
+    const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
+    uint64_t r[kPer2];
+    uint32_t dg[kPer2];
+#pragma unroll
+    for (int j = 0; j < kPer2; ++j) {
+      r[j] = next[j];
       dg[j] = (rec_block(r[j]) >> cshift) & mask;
     }
+    const uint64_t s_next = s + kPartStep;
     scatter_step<kScatter2Threads>(
-        r, dg, valid, f2, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
+        r, dg, valid, f2, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total, a.spare2,
         [&a, local_mask](uint64_t i, uint64_t v) {
           a.buf2[i] = rec_lo(v);
           a.blk2[i] = static_cast<uint16_t>(rec_block(v) & local_mask);
@@ -693,6 +738,9 @@ __global__ __launch_bounds__(kScatter2Threads) void part_scatter2_kernel(PartArg
           uint32_t local;
           W* w = record_target<W>(a, rec_block(v), local);
           rule.add_global(w, local, rec_lo(v), a.k);
+        },
+        [&] {
+          if (s_next < end) load_records(s_next);
         });
   }
 }
