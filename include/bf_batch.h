@@ -86,7 +86,12 @@ bf_status bf_batch_launch_per_filter(bf_batch *b, void *stream);
 
 bf_status bf_batch_info(const bf_batch *b, bf_batch_info_t *out);
 
-/* Frees the plan (after a device synchronization).  NULL is ignored. */
+/* Frees the plan.  The host waits for the plan's own launches
+ * (bf_batch_launch and bf_batch_launch_direct on streams that were not
+ * being captured) and for no other work of the device; the plan's device
+ * memory then returns to the device in stream order.  A graph of the
+ * caller's that captured bf_batch_launch_direct must not run after this
+ * call.  NULL is ignored. */
 bf_status bf_batch_destroy(bf_batch *b);
 
 #ifdef __cplusplus

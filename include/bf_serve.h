@@ -106,7 +106,9 @@ bf_status bf_server_replay_serial(bf_server *srv, const bf_request_t *reqs, uint
 
 bf_status bf_server_stats(const bf_server *srv, bf_server_stats_t *out);
 
-/* Stops the scheduler (after in-flight work completes) and frees the server. */
+/* Stops the scheduler (after in-flight work completes, waiting on the
+ * server's own streams) and frees the server.  Releasing its pinned host
+ * staging (hipHostFree) also waits for the rest of the device's work. */
 bf_status bf_server_destroy(bf_server *srv);
 
 #ifdef __cplusplus

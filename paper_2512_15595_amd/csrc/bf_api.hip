@@ -266,6 +266,36 @@ WordsHome words_home(int device) {
 
 }  // namespace
 
+void* bfhip::lib_alloc(int device, uint64_t bytes, bool* pooled) {
+  *pooled = false;
+  void* p = nullptr;
+  const WordsHome home = words_home(device);
+  if (home.pool != nullptr) {
+    if (hipMallocFromPoolAsync(&p, bytes, home.pool, home.stream) == hipSuccess) {
+      if (hipStreamSynchronize(home.stream) == hipSuccess) {
+        *pooled = true;
+        return p;
+      }
+      (void)hipFreeAsync(p, home.stream);
+      return nullptr;
+    }
+    (void)hipGetLastError();
+  }
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void bfhip::lib_free(int device, void* p, bool pooled) {
+  if (p == nullptr) return;
+  if (pooled)
+    (void)hipFreeAsync(p, words_home(device).stream);
+  else
+    (void)hipFree(p);
+}
+
 bf_status bfhip::alloc_filter_words(bf_filter* f) {
   f->num_bits = f->nbytes * 8;
   f->owns_words = true;

@@ -5,7 +5,9 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <mutex>
 #include <numeric>
+#include <utility>
 #include <vector>
 
 #include "../../include/bf_batch.h"
@@ -50,6 +52,13 @@ struct bf_batch {
   PartLayout part_layout;
   PartKernels part_k;
   void* part_scratch;
+  // device memory from lib_alloc (pooled: released in stream order)
+  int device;
+  bool pooled_filters, pooled_tiles, pooled_scratch;
+  // one event per stream the plan was launched on, recorded after its last
+  // launch there: bf_batch_destroy waits for these and nothing else
+  std::mutex mark_mu;
+  std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
 };
 
 namespace {
@@ -65,10 +74,29 @@ MapSpec class_map(int op, const bf_filter* f, int cls) {
 void free_plan(bf_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
-  if (b->d_filters) (void)hipFree(b->d_filters);
-  if (b->d_tiles) (void)hipFree(b->d_tiles);
-  if (b->part_scratch) (void)hipFree(b->part_scratch);
+  lib_free(b->device, b->d_filters, b->pooled_filters);
+  lib_free(b->device, b->d_tiles, b->pooled_tiles);
+  lib_free(b->device, b->part_scratch, b->pooled_scratch);
+  for (auto& m : b->marks) (void)hipEventDestroy(m.second);
   delete b;
+}
+
+// Records that the plan's work was enqueued on `stream` (not for a stream
+// being captured: such a launch runs when the caller's graph does, which the
+// caller orders against the plan's destruction).
+bf_status mark_launch(bf_batch* b, hipStream_t stream) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return BF_EDEVICE;
+  if (cap != hipStreamCaptureStatusNone) return BF_OK;
+  std::lock_guard<std::mutex> lk(b->mark_mu);
+  hipEvent_t ev = nullptr;
+  for (auto& m : b->marks)
+    if (m.first == stream) ev = m.second;
+  if (ev == nullptr) {
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BF_EDEVICE;
+    b->marks.emplace_back(stream, ev);
+  }
+  return hipEventRecord(ev, stream) == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
 // Partitioned construction for an add plan: the filters' blocks are laid
@@ -198,11 +226,8 @@ bf_status plan_partitioned(bf_batch* b, bf_filter* const* filters, uint32_t nfil
   const uint64_t off_w3 = (off_w2 + work2.size() * sizeof(PartWork) + 255) & ~255ull;
   const uint64_t total = (off_w3 + work3.size() * sizeof(PartWork) + 255) & ~255ull;
   if (work2.size() > 0xffffffffull || work3.size() > 0xffffffffull) return BF_OK;
-  if (hipMalloc(&b->part_scratch, total) != hipSuccess) {
-    (void)hipGetLastError();
-    b->part_scratch = nullptr;
-    return BF_ENOMEM;
-  }
+  b->part_scratch = lib_alloc(b->device, total, &b->pooled_scratch);
+  if (b->part_scratch == nullptr) return BF_ENOMEM;
   uint8_t* base = static_cast<uint8_t*>(b->part_scratch);
   if (hipMemcpy(base + off_pf, pf.data(), pf.size() * sizeof(PartFilter), hipMemcpyHostToDevice) !=
           hipSuccess ||
@@ -362,11 +387,11 @@ bf_status build_tiles(bf_batch* b, bf_filter* const* filters, uint32_t nfilters,
     descs[i].reserved = 0;
   }
   const size_t tiles_bytes = std::max<size_t>(1, tiles.size()) * sizeof(BatchTile);
-  if (hipMalloc(&b->d_filters, descs.size() * sizeof(BatchFilter)) != hipSuccess ||
-      hipMalloc(&b->d_tiles, tiles_bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return BF_ENOMEM;
-  }
+  b->d_filters = static_cast<BatchFilter*>(
+      lib_alloc(b->device, descs.size() * sizeof(BatchFilter), &b->pooled_filters));
+  if (b->d_filters == nullptr) return BF_ENOMEM;
+  b->d_tiles = static_cast<BatchTile*>(lib_alloc(b->device, tiles_bytes, &b->pooled_tiles));
+  if (b->d_tiles == nullptr) return BF_ENOMEM;
   if (hipMemcpy(b->d_filters, descs.data(), descs.size() * sizeof(BatchFilter),
                 hipMemcpyHostToDevice) != hipSuccess ||
       (!tiles.empty() && hipMemcpy(b->d_tiles, tiles.data(), tiles.size() * sizeof(BatchTile),
@@ -421,6 +446,7 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
   b->d_keys = d_keys;
   b->d_out = d_out;
   b->fn = fn;
+  b->device = f0->device;
 
   if (op == BF_OP_ADD) {
     bf_status pst = plan_partitioned(b, filters, nfilters, d_keys, h_offsets);
@@ -459,22 +485,24 @@ bf_status bf_batch_plan(int op, bf_filter* const* filters, uint32_t nfilters,
 bf_status bf_batch_launch(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
   if (b->ntiles == 0 && !b->partitioned) return BF_OK;
-  return hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)) == hipSuccess ? BF_OK
-                                                                                  : BF_EDEVICE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (hipGraphLaunch(b->exec, s) != hipSuccess) return BF_EDEVICE;
+  return mark_launch(b, s);
 }
 
 bf_status bf_batch_launch_direct(bf_batch* b, void* stream) {
   if (b == nullptr) return BF_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
   if (b->partitioned) {
-    const bf_status st = part_launch(b->part, b->part_layout, b->part_k, static_cast<hipStream_t>(stream));
+    const bf_status st = part_launch(b->part, b->part_layout, b->part_k, s);
     if (st != BF_OK) return st;
   }
-  if (b->ntiles == 0) return BF_OK;
-  void* kargs[] = {&b->args};
-  return hipLaunchKernel(b->fn, dim3(b->grid), dim3(kBlockThreads), kargs, 0,
-                         static_cast<hipStream_t>(stream)) == hipSuccess
-             ? BF_OK
-             : BF_EDEVICE;
+  if (b->ntiles > 0) {
+    void* kargs[] = {&b->args};
+    if (hipLaunchKernel(b->fn, dim3(b->grid), dim3(kBlockThreads), kargs, 0, s) != hipSuccess)
+      return BF_EDEVICE;
+  }
+  return b->partitioned || b->ntiles > 0 ? mark_launch(b, s) : BF_OK;
 }
 
 bf_status bf_batch_launch_per_filter(bf_batch* b, void* stream) {
@@ -512,7 +540,11 @@ bf_status bf_batch_info(const bf_batch* b, bf_batch_info_t* out) {
 
 bf_status bf_batch_destroy(bf_batch* b) {
   if (b == nullptr) return BF_OK;
-  bf_status st = hipDeviceSynchronize() == hipSuccess ? BF_OK : BF_EDEVICE;
+  // the host waits for the plan's own launches only (its graph is destroyed
+  // next); its memory then returns to the pool in the library stream's order
+  bf_status st = BF_OK;
+  for (auto& m : b->marks)
+    if (hipEventSynchronize(m.second) != hipSuccess) st = BF_EDEVICE;
   free_plan(b);
   return st;
 }

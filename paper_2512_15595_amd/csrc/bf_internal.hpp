@@ -96,6 +96,15 @@ __global__ void part_zero_kernel(unsigned long long* p, uint64_t n);
 // device, d_words (zeroed, synchronously).  On error the handle is freed.
 bf_status alloc_filter_words(bf_filter* f);
 
+// Device memory of plans and servers (bf_api.hip): taken from the stream-
+// ordered pool of filter words on the library stream and complete when the
+// call returns, or from hipMalloc where the device has no pool (*pooled
+// false); nullptr on failure.  lib_free releases it: pooled memory in the
+// library stream's order, so the caller first waits for (or orders) every
+// use of it; other memory with hipFree, which waits for the whole device.
+void* lib_alloc(int device, uint64_t bytes, bool* pooled);
+void lib_free(int device, void* p, bool pooled);
+
 // bf_add / bf_contains work without the per-filter stream-order bookkeeping
 // (bf_api.hip), for plans and servers that order their own launches.
 bf_status launch_unordered(bf_filter* f, int op, const uint64_t* keys, uint64_t n, uint8_t* out,

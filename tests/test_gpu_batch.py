@@ -202,3 +202,60 @@ def test_batch_auto_add_splits_dense_and_sparse_filters(mode):
             f.close()
     for j in range(len(spec)):
         assert np.array_equal(words[j], want_words[j]), f"filter {j}"
+
+
+@pytest.mark.parametrize("mode", ["graph", "direct"])
+def test_plan_destroy_waits_for_its_own_launches_only(mode):
+    """A plan destroyed right after its launch: the launch still completes
+    with the oracle's results (the plan's memory is released behind it), and
+    the host does not wait for another stream's queued work on an unrelated
+    filter, enqueued after the plan's launch."""
+    bf = _bf()
+    block = 32
+    g = workloads.rng(91)
+    spec = [(8 << 20, 300_000 + int(g.integers(0, 1000))) for _ in range(8)]   # dense: partitioned
+    spec += [(64 << 20, 4_000), (1 << 20, 0), (4 << 20, 2_000)]                 # sparse and empty: tiles
+    counts = np.array([c for _, c in spec], dtype=np.int64)
+    offsets = np.zeros(len(spec) + 1, dtype=np.int64)
+    offsets[1:] = np.cumsum(counts)
+    keys = workloads.uniform_keys(int(offsets[-1]), 92)
+    queries = workloads.mix(keys, workloads.uniform_keys(keys.size, 93), 0.5, 94)
+    params = [dict(num_blocks=sz // block, words_per_block=8, word_bits=32, k=8, seed=700 + i)
+              for i, (sz, _) in enumerate(spec)]
+    want_words, want_out = _oracle(params, offsets, keys, queries)
+    filters = [bf.BloomFilter(**p) for p in params]
+    other = bf.BloomFilter((1 << 30) // block, 8, 32, 8, 3)
+    d_keys = torch.from_numpy(keys.view(np.int64)).to("cuda")
+    d_q = torch.from_numpy(queries.view(np.int64)).to("cuda")
+    d_out = torch.full((queries.size,), 7, dtype=torch.uint8, device="cuda")
+    d_other = torch.from_numpy(workloads.uniform_keys(1 << 26, 95).view(np.int64)).to("cuda")
+    out_other = torch.empty(d_other.numel(), dtype=torch.uint8, device="cuda")
+    s_plan, s_other = torch.cuda.Stream(), torch.cuda.Stream()
+    try:
+        for op in (bf.BF_OP_ADD, bf.BF_OP_CONTAINS):
+            plan = (bf.BatchPlan(op, filters, d_keys, offsets) if op == bf.BF_OP_ADD
+                    else bf.BatchPlan(op, filters, d_q, offsets, d_out))
+            info = plan.info()
+            if op == bf.BF_OP_ADD:
+                assert info.strategy == bf.BF_STRATEGY_PARTITIONED and info.ntiles > 0
+            torch.cuda.synchronize()
+            log(f"plan destroy mode={mode} op={op}: plan launched, ~50 ms of other work queued after it")
+            (plan.launch if mode == "graph" else plan.launch_direct)(stream=s_plan)
+            for _ in range(40):
+                other.contains(d_other, out=out_other, stream=s_other)
+            done_other = torch.cuda.Event()
+            done_other.record(s_other)
+            plan.close()
+            other_pending = not done_other.query()
+            torch.cuda.synchronize()
+            log(f"plan destroy mode={mode} op={op}: other work pending at return: {other_pending}")
+            assert other_pending, "bf_batch_destroy waited for another stream's work"
+        words = [f.words().cpu().numpy() for f in filters]
+        out = d_out.cpu().numpy()
+    finally:
+        for f in filters:
+            f.close()
+        other.close()
+    for j in range(len(params)):
+        assert np.array_equal(words[j], want_words[j]), f"filter {j}"
+    assert np.array_equal(out, want_out)
