@@ -59,6 +59,7 @@ struct bf_batch {
   // launch there: bf_batch_destroy waits for these and nothing else
   std::mutex mark_mu;
   std::vector<std::pair<hipStream_t, hipEvent_t>> marks;
+  bool unmarked;  // a launch whose event could not be recorded: destroy waits for the device
 };
 
 namespace {
@@ -85,18 +86,20 @@ void free_plan(bf_batch* b) {
 // being captured: such a launch runs when the caller's graph does, which the
 // caller orders against the plan's destruction).
 bf_status mark_launch(bf_batch* b, hipStream_t stream) {
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(stream, &cap) != hipSuccess) return BF_EDEVICE;
-  if (cap != hipStreamCaptureStatusNone) return BF_OK;
   std::lock_guard<std::mutex> lk(b->mark_mu);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone) return BF_OK;
   hipEvent_t ev = nullptr;
   for (auto& m : b->marks)
     if (m.first == stream) ev = m.second;
-  if (ev == nullptr) {
-    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return BF_EDEVICE;
+  if (ev == nullptr && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess)
     b->marks.emplace_back(stream, ev);
+  if (ev == nullptr || hipEventRecord(ev, stream) != hipSuccess) {
+    (void)hipGetLastError();
+    b->unmarked = true;  // the work is enqueued: destroy must still wait for it
+    return BF_EDEVICE;
   }
-  return hipEventRecord(ev, stream) == hipSuccess ? BF_OK : BF_EDEVICE;
+  return BF_OK;
 }
 
 // Partitioned construction for an add plan: the filters' blocks are laid
@@ -543,8 +546,12 @@ bf_status bf_batch_destroy(bf_batch* b) {
   // the host waits for the plan's own launches only (its graph is destroyed
   // next); its memory then returns to the pool in the library stream's order
   bf_status st = BF_OK;
-  for (auto& m : b->marks)
-    if (hipEventSynchronize(m.second) != hipSuccess) st = BF_EDEVICE;
+  if (b->unmarked) {
+    if (hipDeviceSynchronize() != hipSuccess) st = BF_EDEVICE;
+  } else {
+    for (auto& m : b->marks)
+      if (hipEventSynchronize(m.second) != hipSuccess) st = BF_EDEVICE;
+  }
   free_plan(b);
   return st;
 }
