@@ -56,6 +56,8 @@ void register_parquet(Registry& r) {
       reinterpret_cast<const void*>(&part_scatter1_kernel<uint32_t, kParquetWords, kParquetK, kZParquet>);
   r.part1_multi_fn[slot] = reinterpret_cast<const void*>(
       &part_scatter1_kernel<uint32_t, kParquetWords, kParquetK, kZParquet, true>);
+  r.part1_chunk_fn[slot] = reinterpret_cast<const void*>(
+      &part_scatter1_kernel<uint32_t, kParquetWords, kParquetK, kZParquet, false, true>);
   r.part2_fn[slot] =
       reinterpret_cast<const void*>(&part_scatter2_kernel<uint32_t, kParquetWords, kParquetK, kZParquet>);
   r.apply_fn[slot] =

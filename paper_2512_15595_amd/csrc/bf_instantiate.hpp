@@ -67,6 +67,8 @@ void register_batch(Registry& r) {
         reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K>);
     r.part1_multi_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
         reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K, 0, true>);
+    r.part1_chunk_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
+        reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K, 0, false, true>);
     r.part2_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =
         reinterpret_cast<const void*>(&part_scatter2_kernel<W, S_WORDS, K>);
     r.apply_fn[batch_index(kOpAdd, kBits, S_WORDS, k_index(K))] =

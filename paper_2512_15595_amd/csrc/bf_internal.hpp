@@ -59,6 +59,7 @@ namespace bfhip {
 struct PartArgs;
 struct PartLayout {
   uint64_t off_buf1, off_buf2, off_blk2, off_fill, nfill1, nfill, total;
+  bool chunk_pass;  // one pass: the first scatter writes the chunk buckets
 };
 struct PartKernels {
   const void* scatter1;
@@ -66,6 +67,7 @@ struct PartKernels {
   const void* scatter2;
   const void* apply;
   uint32_t threads1;  // workgroup size of scatter1
+  const void* scatter1_chunk = nullptr;  // first scatter into chunk buckets (one pass)
 };
 bool partition_applicable(const bf_filter* f, uint64_t n);
 // Workspace bytes a partitioned add of n keys takes from the device pool (0

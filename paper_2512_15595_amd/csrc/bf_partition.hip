@@ -123,6 +123,44 @@ void part_slice(PartArgs& a, PartLayout& L, uint64_t records_per_key) {
   L.total = off;
 }
 
+namespace {
+
+// One pass for a filter of at most kChunkDigits chunks: the first scatter's
+// digit is the chunk (f1 = chunks, no low digit), and it claims runs in the
+// chunk buckets directly, so there is no first record buffer and no second
+// pass.  Every digit then takes 8192 / chunks records of a step on average,
+// at least 64, so the runs still store whole lines.
+void chunk_geometry(uint64_t chunks, uint32_t chunk_shift, uint64_t n, PartArgs& a, PartLayout& L) {
+  a.chunk_shift = chunk_shift;
+  a.chunks = chunks;
+  a.f2 = 1;
+  a.low_bits = 0;
+  a.f1 = static_cast<uint32_t>(chunks);
+  a.q = 1;
+  a.n = n;
+  uint64_t range = (n + 1023) / 1024;
+  range = (range + kPartStep - 1) / kPartStep * kPartStep;
+  a.range1 = std::max<uint64_t>(range, kPartStep);
+  a.cap1 = 0;
+  a.cs1 = 0;
+  a.spare1 = 0;
+  a.cap2 = capacity(static_cast<double>(n) / chunks, 64, 16);
+  const uint64_t split_fill = (2048 + chunks - 1) / chunks;
+  a.apply_split = static_cast<uint32_t>(std::clamp<uint64_t>(
+      std::min<uint64_t>(split_fill, n / chunks / 8192), 1, 1024));
+  uint64_t off = 0;
+  L.off_buf1 = 0;
+  a.spare2 = chunks * a.cap2;
+  part_buf2(L, off, a.spare2);
+  L.nfill1 = 0;
+  L.nfill = chunks;
+  off = align256(off + 8ull * L.nfill);
+  L.total = off;
+  L.chunk_pass = true;
+}
+
+}  // namespace
+
 void part_bind(PartArgs& a, const PartLayout& L, void* base_ptr) {
   uint8_t* base = static_cast<uint8_t*>(base_ptr);
   a.buf1 = reinterpret_cast<uint64_t*>(base + L.off_buf1);
@@ -146,18 +184,20 @@ PartKernels part_kernels(const bf_filter* f) {
     const int idx = csbf_part_index(static_cast<int>(f->word_bits), static_cast<int>(f->s),
                                     static_cast<int>(f->groups), k_index(f->k));
     return PartKernels{r.csbf_part1[idx], nullptr, r.csbf_part2[idx], r.csbf_apply[idx],
-                       kScatter1Threads};
+                       kScatter1Threads, r.csbf_part1_chunk[idx]};
   }
   const int idx = batch_index(0, static_cast<int>(f->word_bits), static_cast<int>(f->s),
                               k_index(f->k));
   const Registry& r = kernel_table(f->salts == kSaltsParquet);
   return PartKernels{r.part1_fn[idx], r.part1_multi_fn[idx], r.part2_fn[idx], r.apply_fn[idx],
-                     kScatter1Threads};
+                     kScatter1Threads, r.part1_chunk_fn[idx]};
 }
 
 bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels& k,
                       hipStream_t stream) {
-  if (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr) return BF_EUNSUPPORTED;
+  if (L.chunk_pass ? (k.scatter1_chunk == nullptr || k.apply == nullptr)
+                   : (k.scatter1 == nullptr || k.scatter2 == nullptr || k.apply == nullptr))
+    return BF_EUNSUPPORTED;
   // shared buckets' fill counters start at zero; slice counts are written
   // by their owners
   const uint64_t zbegin = a.cs1 ? L.nfill1 : 0, zn = L.nfill - zbegin;
@@ -166,10 +206,16 @@ bf_status part_launch(const PartArgs& a, const PartLayout& L, const PartKernels&
                      dim3(kZeroThreads), 0, stream, a.fill1 + zbegin, zn);
   PartArgs copy = a;
   void* args[] = {&copy};
-  if (hipLaunchKernel(k.scatter1, part_grid1(a), dim3(k.threads1), args, 0, stream) != hipSuccess ||
-      hipLaunchKernel(k.scatter2, part_grid2(a), dim3(kScatter2Threads), args, 0, stream) != hipSuccess ||
-      hipLaunchKernel(k.apply, part_grid3(a), dim3(kApplyThreads), args, 0, stream) != hipSuccess)
+  if (L.chunk_pass) {
+    if (hipLaunchKernel(k.scatter1_chunk, part_grid1(a), dim3(kScatter1Threads), args, 0, stream) != hipSuccess ||
+        hipLaunchKernel(k.apply, part_grid3(a), dim3(kApplyThreads), args, 0, stream) != hipSuccess)
+      return BF_EDEVICE;
+  } else if (hipLaunchKernel(k.scatter1, part_grid1(a), dim3(k.threads1), args, 0, stream) != hipSuccess ||
+             hipLaunchKernel(k.scatter2, part_grid2(a), dim3(kScatter2Threads), args, 0, stream) !=
+                 hipSuccess ||
+             hipLaunchKernel(k.apply, part_grid3(a), dim3(kApplyThreads), args, 0, stream) != hipSuccess) {
     return BF_EDEVICE;
+  }
   return hipGetLastError() == hipSuccess ? BF_OK : BF_EDEVICE;
 }
 
@@ -203,6 +249,10 @@ bool single_geometry(const bf_filter* f, uint64_t n, PartArgs& a, PartLayout& L)
   }
   const uint32_t shift = part_chunk_shift(f->s, f->word_bits);
   const uint64_t chunks = (f->num_blocks + (1ull << shift) - 1) >> shift;
+  if (chunks <= static_cast<uint64_t>(kChunkDigits)) {
+    chunk_geometry(chunks, shift, n, a, L);
+    return true;
+  }
   if (!part_geometry(chunks, shift, n, a, L)) return false;
   part_slice(a, L, 1);
   return true;

@@ -18,6 +18,9 @@
 //   scatter2  records -> chunk buckets as (lo32, block within the chunk)
 //             pairs in two arrays;                            [8 in, 6 out]
 //   apply     per chunk: LDS load, LDS atomic OR, store;      [6 in + chunk]
+// A filter of at most kChunkDigits chunks needs one digit: its first pass
+// groups the hashed records by chunk straight into the chunk buckets, and
+// the second pass is skipped.
 // Each scatter step counting-sorts kPartStep records in LDS, so a digit
 // leaves the step as one contiguous run.  Where the run goes:
 //   chunk buckets, and the high-digit buckets of multi-filter plans (whose
@@ -62,6 +65,7 @@ constexpr int kChunkBytes = 64 * 1024;              // LDS bytes owned per chunk
 constexpr int kSpareSlots = 64;                     // spare record slots per record array (one per lane)
 constexpr int kMaxDigits = 1024;                    // digit fan-out limit of the first pass
 constexpr int kMaxDigits2 = 512;                    // ... and of the second (chunks per high digit)
+constexpr int kChunkDigits = 128;                   // chunks up to which the first pass writes chunk buckets
 constexpr int kMaxSlices = 1024;                    // slices one sliced-mode reader concatenates
 constexpr int kVecPerThread = kChunkBytes / 16 / kApplyThreads;  // 16-byte chunk vectors per apply thread
 static_assert(kVecPerThread * 16 * kApplyThreads == kChunkBytes, "apply covers a chunk exactly");
@@ -492,12 +496,17 @@ struct Pass1Dest {
 // one filter, whose fields are read once before the key loop (per-key
 // lookups of the filter inside the loop would make the compiler wait for
 // every outstanding load, the prefetched keys included, before hashing).
-template <typename W, int S_WORDS, int K, int Z, bool MULTI>
+// CHUNK: a filter of at most kChunkDigits chunks, whose digit is the chunk
+// itself: the pass writes the chunk buckets of the apply step directly
+// (6-byte records, runs claimed in the shared buckets), and there is no
+// second pass.
+template <typename W, int S_WORDS, int K, int Z, bool MULTI, bool CHUNK = false>
 __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMaxDigits>& l) {
   constexpr int kPer1 = kPartStep / kScatter1Threads;
   const BlockRule<W, S_WORDS, K, Z> rule;
   const Pass1Dest<kMaxDigits, kScatter1Threads> dst{a, l};
   const uint32_t shift = a.chunk_shift + a.low_bits;
+  const uint32_t local_mask = (1u << a.chunk_shift) - 1;
   uint64_t begin, end, hinit = a.hash_init, base = 0;
   uint32_t nb_lo = a.nb_lo, nb_hi = a.nb_hi_mask;
   if constexpr (MULTI) {
@@ -515,7 +524,9 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
   }
   // The keys of the next step are loaded while this step hashes and sorts
   // (workgroup barriers do not wait for global loads), so their latency is
-  // paid once per workgroup rather than once per step.
+  // paid once per workgroup rather than once per step.  With chunk buckets
+  // they are loaded once the step's claims are done: a claim is then a
+  // returning atomic, whose wait would take them too.
   uint64_t next[kPer1];
   auto load_keys = [&](uint64_t s0) {
     const uint64_t v0 = end - s0 < kPartStep ? end - s0 : kPartStep;
@@ -531,14 +542,17 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
   __builtin_amdgcn_s_waitcnt(wait_vmcnt(0));
   uint32_t par = 0;  // which digit-count buffer this step uses
   for (uint64_t s = begin; s < end; s += kPartStep, par ^= 1u) {
-    // this step's keys were loaded before the previous step's kPer1 record
-    // stores: wait for them only
-    __builtin_amdgcn_s_waitcnt(wait_vmcnt(kPer1));
+    // this step's keys were loaded before the previous step's record stores
+    // (one per record, two with chunk buckets): wait for them only
+    __builtin_amdgcn_s_waitcnt(wait_vmcnt(CHUNK ? 2 * kPer1 : kPer1));
     const uint32_t valid = static_cast<uint32_t>(end - s < kPartStep ? end - s : kPartStep);
     uint64_t key[kPer1];
 #pragma unroll
     for (int j = 0; j < kPer1; ++j) key[j] = next[j];
-    if (s + kPartStep < end) load_keys(s + kPartStep);
+    const uint64_t s_next = s + kPartStep;
+    if constexpr (!CHUNK) {
+      if (s_next < end) load_keys(s_next);
+    }
     uint64_t r[kPer1];
     uint32_t dg[kPer1];
 #pragma unroll
@@ -548,23 +562,44 @@ __device__ __forceinline__ void scatter1_loop(const PartArgs& a, ScatterLds<kMax
       r[j] = (static_cast<uint64_t>(blk) << 32) | static_cast<uint32_t>(h);
       dg[j] = blk >> shift;
     }
-    scatter_step<kScatter1Threads>(
-        r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total, a.spare1,
-        [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; },
-        [shift](uint64_t v) { return rec_block(v) >> shift; },
-        [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); },
-        [&](uint64_t v) {
-          uint32_t local;
-          W* w = record_target<W>(a, rec_block(v), local);
-          rule.add_global(w, local, rec_lo(v), a.k);
-        },
-        [] {});
+    auto overflow = [&](uint64_t v) {
+      uint32_t local;
+      W* w = record_target<W>(a, rec_block(v), local);
+      rule.add_global(w, local, rec_lo(v), a.k);
+    };
+    auto digit_of = [shift](uint64_t v) { return rec_block(v) >> shift; };
+    if constexpr (CHUNK) {
+      scatter_step<kScatter1Threads>(
+          r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
+          a.spare2,
+          [&a, local_mask](uint64_t i, uint64_t v) {
+            a.buf2[i] = rec_lo(v);
+            a.blk2[i] = static_cast<uint16_t>(rec_block(v) & local_mask);
+          },
+          digit_of,
+          [&a](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) {
+            const uint64_t b = atomicAdd(&a.fill2[d], static_cast<unsigned long long>(c));
+            gb = bucket2_base(a, d) + b;
+            rm = run_room(b, c, bucket2_cap(a, d));
+          },
+          overflow,
+          [&] {
+            if (s_next < end) load_keys(s_next);
+          });
+    } else {
+      scatter_step<kScatter1Threads>(
+          r, dg, valid, a.f1, l.stage, l.cnt[par], l.cnt[par ^ 1], l.start, l.gbase, l.room, &l.total,
+          a.spare1, [&a](uint64_t i, uint64_t v) { a.buf1[i] = v; }, digit_of,
+          [&dst](uint32_t d, uint32_t c, uint64_t& gb, uint32_t& rm) { dst.claim(d, c, gb, rm); }, overflow,
+          [] {});
+    }
   }
-  dst.publish();
+  if constexpr (!CHUNK) dst.publish();
 }
 
-// MULTI: the kernel of multi-filter plans (one work item per workgroup).
-template <typename W, int S_WORDS, int K, int Z = 0, bool MULTI = false>
+// MULTI: the kernel of multi-filter plans (one work item per workgroup);
+// CHUNK: the one-pass form for filters of at most kChunkDigits chunks.
+template <typename W, int S_WORDS, int K, int Z = 0, bool MULTI = false, bool CHUNK = false>
 __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArgs a) {
   __shared__ __attribute__((aligned(16))) ScatterLds<kMaxDigits> l;
   for (uint32_t d = threadIdx.x; d < a.f1; d += kScatter1Threads) {
@@ -573,7 +608,7 @@ __global__ __launch_bounds__(kScatter1Threads) void part_scatter1_kernel(PartArg
     l.fill[d] = 0;
   }
   __syncthreads();
-  scatter1_loop<W, S_WORDS, K, Z, MULTI>(a, l);
+  scatter1_loop<W, S_WORDS, K, Z, MULTI, CHUNK>(a, l);
 }
 
 // First pass of the classic filter: each key gives K records, one per

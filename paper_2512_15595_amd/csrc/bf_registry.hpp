@@ -58,6 +58,7 @@ struct Registry {
   const void* batch_fn[kBatchRegistrySize];  // persistent batched kernels
   const void* part1_fn[kBatchRegistrySize];  // partitioned add: first scatter (op slot 0)
   const void* part1_multi_fn[kBatchRegistrySize];  // ... of a multi-filter plan
+  const void* part1_chunk_fn[kBatchRegistrySize];  // ... into chunk buckets (one pass)
   const void* part2_fn[kBatchRegistrySize];  // partitioned add: second scatter
   const void* apply_fn[kBatchRegistrySize];  // partitioned add: per-chunk apply
 };

@@ -27,6 +27,7 @@ void register_csbf_part(VariantRegistry& r) {
     constexpr int kBits = 8 * static_cast<int>(sizeof(W));
     const int idx = csbf_part_index(kBits, S_WORDS, Z, k_index(K));
     r.csbf_part1[idx] = reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K, Z>);
+    r.csbf_part1_chunk[idx] = reinterpret_cast<const void*>(&part_scatter1_kernel<W, S_WORDS, K, Z, false, true>);
     r.csbf_part2[idx] = reinterpret_cast<const void*>(&part_scatter2_kernel<W, S_WORDS, K, Z>);
     r.csbf_apply[idx] = reinterpret_cast<const void*>(&part_apply_kernel<W, S_WORDS, K, Z>);
   }

@@ -59,6 +59,7 @@ struct VariantRegistry {
   const void* classic_part2;
   const void* classic_apply;
   const void* csbf_part1[kCsbfPartSize];
+  const void* csbf_part1_chunk[kCsbfPartSize];  // one pass into chunk buckets
   const void* csbf_part2[kCsbfPartSize];
   const void* csbf_apply[kCsbfPartSize];
 };
