@@ -92,8 +92,8 @@ typedef struct bf_filter bf_filter; /* opaque handle, owns the device words */
  *                   radix-partitions the keys by 64 KiB filter chunk and
  *                   updates each chunk in LDS, so a bulk add performs no
  *                   global atomics; it takes a workspace of 14-22 bytes per key
- *                   (about 6 for a filter of at most 128 chunks, which is
- *                   partitioned in one pass)
+ *                   (about 6 for a filter of at most 1024 chunks, 64 MiB,
+ *                   which is partitioned in one pass)
  *                   from a per-device stream-ordered memory pool and returns
  *                   it at its end on the same stream (no device
  *                   synchronization; the pool keeps its peak size reserved
@@ -213,7 +213,7 @@ bf_status bf_set_mapping_ex(bf_filter *f, int op, const bf_mapping_t *m);
  * choice resolved by the measured crossover (partitioned from about 1.5 M
  * keys + filter bytes / 80; for the classic layout n counts k records per
  * key).  For callers that plan workspace memory (14-22 bytes per key for a
- * partitioned add, about 6 into a filter of at most 128 chunks).  Host only:
+ * partitioned add, about 6 into a filter of at most 64 MiB).  Host only:
  * enqueues nothing and touches no device.
  * BF_EINVAL if f or out is NULL. */
 bf_status bf_add_strategy(const bf_filter *f, uint64_t n, uint32_t *out);
@@ -238,10 +238,11 @@ bf_status bf_tuned_mapping(int op, uint64_t num_blocks, uint32_t words_per_block
  * library's code on the first call there and kept until the process ends.
  * An add the automatic rule builds directly (one atomic OR group per key)
  * needs no workspace and is bf_add itself.  A partitioned add must fit one
- * pass of the array (at most 2^28 records; the workspace is about 14-22
- * bytes per key, the most for few keys into a large filter, so up to about
- * 16 M keys into filters of 64 MiB or less and 12 M into a 1 GiB filter;
- * about 6 bytes per key into a filter of at most 128 chunks, so ~44 M):
+ * pass of the array (at most 2^28 records; the workspace is about 6 bytes
+ * per key into a filter of at most 64 MiB, which is partitioned in one
+ * pass, so up to about 43 M keys, and 14-22 bytes per key into a larger
+ * one, the most for few keys into a large filter, so about 12 M into a
+ * 1 GiB filter):
  * larger adds give BF_ESCRATCH with nothing enqueued.  Calls on one device
  * share the array, which keeps the last call's contents (the kernels clear
  * the counters they need): outside graph capture the library orders them

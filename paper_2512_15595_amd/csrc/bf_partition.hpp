@@ -18,9 +18,9 @@
 //   scatter2  records -> chunk buckets as (lo32, block within the chunk)
 //             pairs in two arrays;                            [8 in, 6 out]
 //   apply     per chunk: LDS load, LDS atomic OR, store;      [6 in + chunk]
-// A filter of at most kChunkDigits chunks needs one digit: its first pass
-// groups the hashed records by chunk straight into the chunk buckets, and
-// the second pass is skipped.
+// A filter of at most kChunkDigits chunks (64 MiB) needs one digit: its
+// first pass groups the hashed records by chunk straight into the chunk
+// buckets, and the second pass is skipped.
 // Each scatter step counting-sorts kPartStep records in LDS, so a digit
 // leaves the step as one contiguous run.  Where the run goes:
 //   chunk buckets, and the high-digit buckets of multi-filter plans (whose
@@ -65,7 +65,7 @@ constexpr int kChunkBytes = 64 * 1024;              // LDS bytes owned per chunk
 constexpr int kSpareSlots = 64;                     // spare record slots per record array (one per lane)
 constexpr int kMaxDigits = 1024;                    // digit fan-out limit of the first pass
 constexpr int kMaxDigits2 = 512;                    // ... and of the second (chunks per high digit)
-constexpr int kChunkDigits = 128;                   // chunks up to which the first pass writes chunk buckets
+constexpr int kChunkDigits = kMaxDigits;            // chunks up to which the first pass writes chunk buckets
 constexpr int kMaxSlices = 1024;                    // slices one sliced-mode reader concatenates
 constexpr int kVecPerThread = kChunkBytes / 16 / kApplyThreads;  // 16-byte chunk vectors per apply thread
 static_assert(kVecPerThread * 16 * kApplyThreads == kChunkBytes, "apply covers a chunk exactly");
