@@ -221,6 +221,34 @@ def test_partitioned_add_bit_exact(s, S):
             f.close()
 
 
+
+@pytest.mark.parametrize("chunks,extra_blocks", [(1024, 0), (1024, 1)])
+def test_partitioned_add_at_the_one_pass_limit(chunks, extra_blocks):
+    """Filters of exactly 1024 chunks of 64 KiB (partitioned in one pass) and
+    of one block more (1025 chunks, the last holding one block: two passes)
+    build the oracle's words, with a ragged key count and a second add."""
+    bf = _bf()
+    nblocks = chunks * (65536 // 32) + extra_blocks
+    params = dict(num_blocks=nblocks, words_per_block=8, word_bits=32, k=8, seed=chunks + extra_blocks)
+    g = workloads.rng(nblocks)
+    adds = g.integers(0, 2**64, size=1_500_001, dtype=np.uint64)
+    more = g.integers(0, 2**64, size=700_003, dtype=np.uint64)
+    queries = np.concatenate([adds[:5000], g.integers(0, 2**64, size=20_000, dtype=np.uint64)])
+    log(f"one-pass limit: {chunks} chunks + {extra_blocks} blocks, {adds.size} + {more.size} keys")
+    ref = oracle.OracleFilter(**params)
+    ref.add(adds)
+    ref.add(more)
+    f = bf.BloomFilter(**params)
+    try:
+        f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        f.add(to_device(adds))
+        f.add(to_device(more))
+        assert np.array_equal(f.words().cpu().numpy(), ref.bytes)
+        assert np.array_equal(f.contains(to_device(queries)).cpu().numpy(), ref.contains(queries))
+        torch.cuda.synchronize()
+    finally:
+        f.close()
+
 def test_auto_strategy_matches_direct():
     """Auto picks the partitioned path for a dense batch; words equal those
     of the direct path."""
