@@ -107,6 +107,41 @@ def test_noalloc_rejects_adds_beyond_the_array_and_enqueues_nothing():
         f.close()
 
 
+
+def test_noalloc_one_pass_limit_of_a_64_mib_filter():
+    """A filter of at most 64 MiB (1024 chunks) is partitioned in one pass,
+    about 6 bytes of workspace per key: 40 M keys fit the array and give
+    bf_add's words (sampled blocks against the oracle), 46 M do not
+    (BF_ESCRATCH, nothing enqueued)."""
+    bf = _bf()
+    lib = _lib()
+    nb = (64 << 20) // 32
+    keys = workloads.uniform_keys(46_000_000, 31)
+    d = _dev(keys)
+    f_na = bf.BloomFilter(nb, 8, 32, 8, 13)
+    f_ref = bf.BloomFilter(nb, 8, 32, 8, 13)
+    s = torch.cuda.current_stream().cuda_stream
+    try:
+        for f in (f_na, f_ref):
+            f.set_mapping(bf.BF_OP_ADD, strategy=bf.BF_STRATEGY_PARTITIONED)
+        log("noalloc one-pass limit: 46 M keys into 64 MiB (refused)")
+        assert lib.bf_add_noalloc(f_na.handle, d.data_ptr(), keys.size, s) == bf.BF_ESCRATCH
+        torch.cuda.synchronize()
+        assert int(f_na.words().count_nonzero().item()) == 0
+        n = 40_000_000
+        log("noalloc one-pass limit: 40 M keys into 64 MiB (accepted)")
+        assert lib.bf_add_noalloc(f_na.handle, d.data_ptr(), n, s) == 0
+        f_ref.add(d[:n])
+        got, want = f_na.words().cpu().numpy(), f_ref.words().cpu().numpy()
+        torch.cuda.synchronize()
+        assert np.array_equal(got, want)
+        sel = workloads.rng(32).choice(nb, size=2048, replace=False).astype(np.uint64)
+        rows = oracle.block_words(nb, 8, 32, 8, 13, keys[:n], sel)
+        assert np.array_equal(got.reshape(nb, 32)[sel.astype(np.int64)], rows)
+    finally:
+        f_na.close()
+        f_ref.close()
+
 def test_noalloc_calls_on_two_streams_do_not_overlap():
     """Two filters, two streams, no caller events: the library orders the
     calls that share the array, so both filters get the oracle's words."""
